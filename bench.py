@@ -1,0 +1,230 @@
+"""Benchmark of the Siddon DRR hot path on one MI355X.
+
+Workload: 512 x 512 x 133 CT at 0.7 x 0.7 x 2.5 mm (seeded ellipsoid
+phantom with a bone-like shell), 256 x 256 detector at 1.4 mm, SDD 1020 mm,
+256 random poses (angles +-pi/6, shifts +-30 mm) per batch.
+
+One step = one pass of the hot path over the batch:
+  forward     all 256 DRRs in one launch                 (timed: fwd)
+  fwd + bwd   all 256 DRRs, negative ZNCC against per-pose targets and the
+              pose gradient, in one fused tracing launch  (timed: fwd+bwd)
+The printed JSON line reports forward DRRs/s as `value`, with fwd+bwd
+throughput, voxel-gather rates, latency percentiles, the HBM roofline of the
+forward kernel and the FP64 CPU oracle timed on a bounded sample.
+"""
+
+from __future__ import annotations
+
+import argparse
+import ctypes
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+HBM_PEAK_GBS = 8000.0
+METRIC = ("DRRs/sec and Gvoxel-gathers/s (fwd, fwd+bwd) at 512²×133 CT, "
+          "256² det; p99 ms")
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--poses", type=int, default=256)
+    ap.add_argument("--latency-reps", type=int, default=200)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=20.0,
+                    help="approximate CPU time (thread-seconds) for the oracle sample")
+    ap.add_argument("--only", choices=["fwd", "fwdbwd"], default=None,
+                    help="time one phase only (for profiling runs)")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run only a plain 1 GiB device-to-device copy (reference kernel "
+                         "for scaling hardware byte counters)")
+    return ap.parse_args()
+
+
+def copy_calibration():
+    import torch
+    n = (1 << 30) // 4
+    a = torch.ones(n, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
+                      "launches": 3}), flush=True)
+
+
+def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
+    """The FP64 oracle on host cores over whole DRRs of the same workload."""
+    import oracle
+    nthreads = oracle.max_threads()
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    p64 = poses.astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.render(grid, p64[:1], det_px, det_px, pitch, pitch, nthreads=nthreads)
+    first = time.perf_counter() - t0
+    n = int(max(1, min(len(p64) - 1, round(cpu_seconds / max(first * nthreads, 1e-6)))))
+    t0 = time.perf_counter()
+    oracle.render(grid, p64[1:1 + n], det_px, det_px, pitch, pitch, nthreads=nthreads)
+    dt = time.perf_counter() - t0
+    return {"value": n / dt, "unit": "DRRs/s", "cores": nthreads, "kind": "oracle",
+            "sample": f"{n} whole {det_px}x{det_px} DRRs of the benchmark poses "
+                      f"({n * det_px * det_px} rays), FP64 sort-based Siddon, "
+                      f"{dt:.2f} s wall on {nthreads} threads"}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported "
+              "(poses are independent: the multi-GPU layout replicates the volume and deals "
+              "poses out, with no communication)", file=sys.stderr)
+        sys.exit(2)
+    if args.copy_calibration:
+        copy_calibration()
+        return
+
+    import torch
+    import paper_2208_12737_amd as P
+    from synth import make_phantom, random_poses
+
+    dev = torch.device("cuda")
+    torch.cuda.set_device(0)
+    H = W = 256
+    pitch, sdd = 1.4, 1020.0
+    nb = args.poses
+    print(f"[bench] building 512x512x133 phantom", file=sys.stderr, flush=True)
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=dev)
+    det = P.Detector(H, W, pitch, pitch)
+    poses_np = random_poses(nb, math.pi / 6, 30.0, sdd, seed=1)
+    gt_np = random_poses(nb, math.pi / 6, 30.0, sdd, seed=2)
+    poses = torch.from_numpy(poses_np).to(dev)
+    gt = torch.from_numpy(gt_np).to(dev)
+    # moving poses for fwd+bwd: ground truth plus a seeded offset
+    off = np.random.default_rng(3).uniform(-1, 1, (nb, 7)).astype(np.float32)
+    off[:, :3] *= math.radians(5.0)
+    off[:, 3:6] *= 5.0
+    off[:, 6] = 0.0
+    moving = torch.from_numpy(gt_np + off).to(dev)
+    targets = P.render(vol, gt, det)
+    torch.cuda.synchronize()
+
+    # algorithmic work: gathers counted by the renderer's counting mode
+    _, cnt = P.render_count(vol, poses, det)
+    _, cnt_m = P.render_count(vol, moving, det)
+    gathers_fwd = int(cnt.to(torch.int64).sum().item())
+    gathers_bwd = int(cnt_m.to(torch.int64).sum().item())
+    pixels = nb * H * W
+    bytes_fwd = 4 * gathers_fwd + 4 * pixels
+
+    stream = torch.cuda.current_stream()
+    img = torch.empty((nb, H, W), dtype=torch.float32, device=dev)
+    import paper_2208_12737_amd._lib as L
+    ws_n = L.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), nb)
+    ws = torch.empty(ws_n, dtype=torch.uint8, device=dev)
+    loss = torch.empty((nb,), dtype=torch.float32, device=dev)
+    grad = torch.empty((nb, 7), dtype=torch.float32, device=dev)
+
+    def fwd():
+        L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc),
+               ctypes.byref(det.desc), poses.data_ptr(), nb, img.data_ptr(), None,
+               stream.cuda_stream)
+
+    def fwdbwd():
+        L.call("drr_render_ncc_grad", vol.packed.data_ptr(), ctypes.byref(vol.desc),
+               ctypes.byref(det.desc), moving.data_ptr(), nb, targets.data_ptr(), H * W, None,
+               loss.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
+
+    phases = [("fwd", fwd), ("fwdbwd", fwdbwd)]
+    if args.only:
+        phases = [p for p in phases if p[0] == args.only]
+
+    for _ in range(args.warmup):
+        for _, f in phases:
+            f()
+    torch.cuda.synchronize()
+
+    ev = {name: [] for name, _ in phases}
+    step_ev = []
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        s0 = torch.cuda.Event(enable_timing=True)
+        s0.record(stream)
+        for name, f in phases:
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            f()
+            b.record(stream)
+            ev[name].append((a, b))
+        s1 = torch.cuda.Event(enable_timing=True)
+        s1.record(stream)
+        step_ev.append((s0, s1))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    times = {k: np.array([a.elapsed_time(b) for a, b in v]) for k, v in ev.items()}
+    step_ms = np.array([a.elapsed_time(b) for a, b in step_ev])
+
+    # single-DRR latency (plain forward path, one pose per launch)
+    lat = []
+    one = poses[:1].clone()
+    img1 = torch.empty((1, H, W), dtype=torch.float32, device=dev)
+    for i in range(args.latency_reps + 10):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc),
+               ctypes.byref(det.desc), one.data_ptr(), 1, img1.data_ptr(), None,
+               stream.cuda_stream)
+        torch.cuda.synchronize()
+        if i >= 10:
+            lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat)
+
+    res = {"metric": METRIC, "unit": "DRRs/s", "n_gpus": 1, "steps": args.steps,
+           "warmup": args.warmup, "ms_per_step": float(step_ms.mean()),
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "data": "synthetic (seeded ellipsoid phantom, random poses)",
+           "config": {"workload": "ct512x512x133_det256_poses256", "volume": [512, 512, 133],
+                      "spacing_mm": [0.7, 0.7, 2.5], "detector": [H, W], "pitch_mm": pitch,
+                      "sdd_mm": sdd, "poses_per_batch": nb}}
+    if "fwd" in times:
+        t_fwd = times["fwd"].mean() / 1e3
+        res["value"] = nb / t_fwd
+        res["fwd_ms_per_batch"] = float(times["fwd"].mean())
+        res["gvox_gathers_per_s_fwd"] = gathers_fwd / t_fwd / 1e9
+        res["gathers_per_ray_fwd"] = gathers_fwd / pixels
+        achieved = bytes_fwd / t_fwd / 1e9
+        res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                           "kernel": "render_flat<8,2,2,kImage>",
+                           "bytes_per_launch": bytes_fwd}
+    if "fwdbwd" in times:
+        t_fb = times["fwdbwd"].mean() / 1e3
+        res["fwdbwd_drrs_per_s"] = nb / t_fb
+        res["fwdbwd_ms_per_batch"] = float(times["fwdbwd"].mean())
+        res["gvox_gathers_per_s_fwdbwd"] = gathers_bwd / t_fb / 1e9
+        if "value" not in res:
+            res["value"] = nb / t_fb
+    res["p50_ms"] = float(np.percentile(step_ms, 50))
+    res["p99_ms"] = float(np.percentile(step_ms, 99))
+    res["single_drr_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                    "p99": float(np.percentile(lat, 99)),
+                                    "drrs_per_s": float(1e3 / lat.mean())}
+    res["wall_s_timed"] = wall
+    if not args.no_cpu_baseline:
+        print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
+        res["cpu_baseline"] = cpu_baseline(ph, poses_np, H, pitch, args.cpu_seconds)
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,294 @@
+// C-ABI entry points of libdrr.so (declared in include/drr.h): volume
+// packing, forward render, Jacobian / retrace pose gradients, ZNCC loss and
+// the fused registration objective.  Host code here validates arguments and
+// enqueues kernels; it never allocates device memory.
+#include <string.h>
+
+#include "common.hpp"
+#include "reduce_kernels.hpp"
+
+namespace drr {
+
+static thread_local char g_err[512] = "";
+
+int32_t fail(int32_t code, const char* fmt, ...)
+{
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(g_err, sizeof g_err, fmt, ap);
+    va_end(ap);
+    return code;
+}
+
+int32_t check_launch(const char* what)
+{
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(DRR_EHIP, "%s: %s", what, hipGetErrorString(e));
+    return DRR_OK;
+}
+
+// Default launch shape of the flat entry points: 8 x 8-pixel wave tiles,
+// 2 x 2 waves per workgroup (16 x 16 pixels, 256 threads).
+constexpr int kTW = 8, kWX = 2, kWY = 2;
+using DefaultShape = TileShape<kTW, kWX, kWY>;
+
+struct FlatGrid {
+    int tiles_x, tiles_y, wg_per_pose;
+};
+
+static FlatGrid flat_grid(const drr_detector_desc& d)
+{
+    FlatGrid g;
+    g.tiles_x = (d.width + DefaultShape::px_w - 1) / DefaultShape::px_w;
+    g.tiles_y = (d.height + DefaultShape::px_h - 1) / DefaultShape::px_h;
+    g.wg_per_pose = g.tiles_x * g.tiles_y;
+    return g;
+}
+
+template <int MODE>
+static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
+                           const drr_detector_desc& det, const float* poses, int32_t n_poses,
+                           float* image, float* jac, int32_t* counts, const float* aux,
+                           int64_t aux_stride, double* partials, hipStream_t stream)
+{
+    const FlatGrid g = flat_grid(det);
+    const uint64_t blocks = (uint64_t)g.wg_per_pose * (uint64_t)n_poses;
+    if (blocks > 0x7FFFFFFFull) return fail(DRR_ENOTSUP, "too many tiles in one launch");
+    hipLaunchKernelGGL((render_flat<kTW, kWX, kWY, MODE>), dim3((unsigned)blocks),
+                       dim3(DefaultShape::threads), 0, stream, vol_args(packed, vol),
+                       det_args(det), poses, g.tiles_x, g.wg_per_pose, image, jac, counts, aux,
+                       aux_stride, partials);
+    return check_launch("render kernel launch");
+}
+
+static size_t chunks_of(int64_t hw) { return (size_t)((hw + kChunkPixels - 1) / kChunkPixels); }
+
+}  // namespace drr
+
+using namespace drr;
+
+extern "C" {
+
+const char* drr_last_error(void) { return g_err; }
+
+int32_t drr_version(void) { return 10000; }
+
+const char* drr_status_string(int32_t s)
+{
+    switch (s) {
+    case DRR_OK: return "ok";
+    case DRR_EINVAL: return "invalid argument";
+    case DRR_ENOMEM: return "workspace too small or allocation failed";
+    case DRR_EHIP: return "HIP runtime error";
+    case DRR_ENOTSUP: return "unsupported size";
+    default: return "unknown status";
+    }
+}
+
+size_t drr_volume_packed_bytes(const drr_volume_desc* vol)
+{
+    if (validate_volume(vol) != DRR_OK) return 0;
+    return (size_t)(packed_elems(*vol) * 4ull);
+}
+
+int32_t drr_volume_pack(const float* src, void* packed, const drr_volume_desc* vol, void* stream)
+{
+    int32_t st = validate_volume(vol);
+    if (st) return st;
+    if (!src || !packed) return fail(DRR_EINVAL, "volume_pack: NULL pointer");
+    const uint64_t total = packed_elems(*vol);
+    const unsigned blocks = (unsigned)((total + 255) / 256);
+    hipLaunchKernelGGL(k_pack, dim3(blocks), dim3(256), 0, as_stream(stream), src, (float*)packed,
+                       vol->nx, vol->ny, vol->nz, total);
+    return check_launch("volume_pack");
+}
+
+static int32_t common_render_checks(const void* packed, const drr_volume_desc* vol,
+                                    const drr_detector_desc* det, const float* poses,
+                                    int32_t n_poses)
+{
+    int32_t st = validate_volume(vol);
+    if (st) return st;
+    st = validate_detector(det);
+    if (st) return st;
+    if (n_poses < 0) return fail(DRR_EINVAL, "n_poses must be >= 0 (got %d)", n_poses);
+    if (n_poses > 0 && (!packed || !poses)) return fail(DRR_EINVAL, "NULL volume or poses");
+    return DRR_OK;
+}
+
+int32_t drr_render(const void* packed, const drr_volume_desc* vol, const drr_detector_desc* det,
+                   const float* poses, int32_t n_poses, float* image, float* jac, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    if (n_poses == 0) return DRR_OK;
+    if (!image) return fail(DRR_EINVAL, "render: image is NULL");
+    if (jac)
+        return launch_flat<kJac>(packed, *vol, *det, poses, n_poses, image, jac, nullptr, nullptr,
+                                 0, nullptr, as_stream(stream));
+    return launch_flat<kImage>(packed, *vol, *det, poses, n_poses, image, nullptr, nullptr,
+                               nullptr, 0, nullptr, as_stream(stream));
+}
+
+int32_t drr_render_count(const void* packed, const drr_volume_desc* vol,
+                         const drr_detector_desc* det, const float* poses, int32_t n_poses,
+                         float* image, int32_t* counts, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    if (n_poses == 0) return DRR_OK;
+    if (!image || !counts) return fail(DRR_EINVAL, "render_count: NULL output");
+    return launch_flat<kCount>(packed, *vol, *det, poses, n_poses, image, nullptr, counts,
+                               nullptr, 0, nullptr, as_stream(stream));
+}
+
+size_t drr_backward_workspace_bytes(const drr_detector_desc* det, int32_t n_poses)
+{
+    if (validate_detector(det) != DRR_OK || n_poses < 0) return 0;
+    const int64_t hw = (int64_t)det->height * det->width;
+    size_t per = chunks_of(hw);
+    size_t tiles = (size_t)flat_grid(*det).wg_per_pose;
+    if (tiles > per) per = tiles;
+    return per * (size_t)n_poses * 7 * sizeof(double);
+}
+
+int32_t drr_render_backward(const drr_detector_desc* det, int32_t n_poses, const float* jac,
+                            const float* grad_image, float* grad_pose, void* workspace,
+                            size_t workspace_bytes, void* stream)
+{
+    int32_t st = validate_detector(det);
+    if (st) return st;
+    if (n_poses < 0) return fail(DRR_EINVAL, "n_poses must be >= 0");
+    if (n_poses == 0) return DRR_OK;
+    if (!jac || !grad_image || !grad_pose || !workspace)
+        return fail(DRR_EINVAL, "render_backward: NULL pointer");
+    if (workspace_bytes < drr_backward_workspace_bytes(det, n_poses))
+        return fail(DRR_ENOMEM, "render_backward: workspace of %zu bytes, need %zu",
+                    workspace_bytes, drr_backward_workspace_bytes(det, n_poses));
+    const int64_t hw = (int64_t)det->height * det->width;
+    const int chunks = (int)chunks_of(hw);
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(k_jac_dot, dim3(chunks, n_poses), dim3(kReduceThreads), 0, s, jac,
+                       grad_image, hw, chunks, (double*)workspace);
+    if ((st = check_launch("jac_dot"))) return st;
+    hipLaunchKernelGGL(k_grad_finalize, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                       (const double*)workspace, chunks, grad_pose);
+    return check_launch("grad_finalize");
+}
+
+int32_t drr_render_backward_retrace(const void* packed, const drr_volume_desc* vol,
+                                    const drr_detector_desc* det, const float* poses,
+                                    int32_t n_poses, const float* grad_image, float* grad_pose,
+                                    void* workspace, size_t workspace_bytes, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    if (n_poses == 0) return DRR_OK;
+    if (!grad_image || !grad_pose || !workspace)
+        return fail(DRR_EINVAL, "render_backward_retrace: NULL pointer");
+    if (workspace_bytes < drr_backward_workspace_bytes(det, n_poses))
+        return fail(DRR_ENOMEM, "render_backward_retrace: workspace too small");
+    const int64_t hw = (int64_t)det->height * det->width;
+    hipStream_t s = as_stream(stream);
+    st = launch_flat<kRetrace>(packed, *vol, *det, poses, n_poses, nullptr, nullptr, nullptr,
+                               grad_image, hw, (double*)workspace, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_grad_finalize, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                       (const double*)workspace, flat_grid(*det).wg_per_pose, grad_pose);
+    return check_launch("grad_finalize");
+}
+
+size_t drr_ncc_workspace_bytes(int32_t n_poses, int64_t hw)
+{
+    if (n_poses < 0 || hw < 1) return 0;
+    return chunks_of(hw) * (size_t)n_poses * 5 * sizeof(double);
+}
+
+int32_t drr_ncc_forward(const float* image, const float* target, int64_t target_stride,
+                        int32_t n_poses, int64_t hw, double* stats, float* loss,
+                        void* workspace, size_t workspace_bytes, void* stream)
+{
+    if (n_poses < 0 || hw < 2) return fail(DRR_EINVAL, "ncc_forward: n_poses >= 0, hw >= 2");
+    if (target_stride != 0 && target_stride != hw)
+        return fail(DRR_EINVAL, "ncc_forward: target_stride must be 0 or hw");
+    if (n_poses == 0) return DRR_OK;
+    if (!image || !target || !stats || !loss || !workspace)
+        return fail(DRR_EINVAL, "ncc_forward: NULL pointer");
+    if (workspace_bytes < drr_ncc_workspace_bytes(n_poses, hw))
+        return fail(DRR_ENOMEM, "ncc_forward: workspace too small");
+    const int chunks = (int)chunks_of(hw);
+    hipStream_t s = as_stream(stream);
+    hipLaunchKernelGGL(k_ncc_moments, dim3(chunks, n_poses), dim3(kReduceThreads), 0, s, image,
+                       target, target_stride, hw, chunks, (double*)workspace);
+    int32_t st = check_launch("ncc_moments");
+    if (st) return st;
+    hipLaunchKernelGGL(k_ncc_stats, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                       (const double*)workspace, chunks, (double)hw, stats, loss);
+    return check_launch("ncc_stats");
+}
+
+int32_t drr_ncc_backward(const float* image, const float* target, int64_t target_stride,
+                         const double* stats, const float* grad_loss, int32_t n_poses,
+                         int64_t hw, float* grad_image, void* stream)
+{
+    if (n_poses < 0 || hw < 2) return fail(DRR_EINVAL, "ncc_backward: n_poses >= 0, hw >= 2");
+    if (target_stride != 0 && target_stride != hw)
+        return fail(DRR_EINVAL, "ncc_backward: target_stride must be 0 or hw");
+    if (n_poses == 0) return DRR_OK;
+    if (!image || !target || !stats || !grad_loss || !grad_image)
+        return fail(DRR_EINVAL, "ncc_backward: NULL pointer");
+    const unsigned bx = (unsigned)((hw + kReduceThreads - 1) / kReduceThreads);
+    hipLaunchKernelGGL(k_ncc_backward, dim3(bx, n_poses), dim3(kReduceThreads), 0,
+                       as_stream(stream), image, target, target_stride, stats, grad_loss, hw,
+                       (double)hw, grad_image);
+    return check_launch("ncc_backward");
+}
+
+size_t drr_ncc_grad_workspace_bytes(const drr_detector_desc* det, int32_t n_poses)
+{
+    if (validate_detector(det) != DRR_OK || n_poses < 0) return 0;
+    return (size_t)flat_grid(*det).wg_per_pose * (size_t)n_poses * kNccSums * sizeof(double);
+}
+
+int32_t drr_render_ncc_grad(const void* packed, const drr_volume_desc* vol,
+                            const drr_detector_desc* det, const float* poses, int32_t n_poses,
+                            const float* target, int64_t target_stride, float* image,
+                            float* loss, float* grad_pose, void* workspace,
+                            size_t workspace_bytes, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    const int64_t hw = (int64_t)det->height * det->width;
+    if (target_stride != 0 && target_stride != hw)
+        return fail(DRR_EINVAL, "render_ncc_grad: target_stride must be 0 or H*W");
+    if (hw < 2) return fail(DRR_EINVAL, "render_ncc_grad: need at least 2 pixels");
+    if (n_poses == 0) return DRR_OK;
+    if (!target || !loss || !grad_pose || !workspace)
+        return fail(DRR_EINVAL, "render_ncc_grad: NULL pointer");
+    if (workspace_bytes < drr_ncc_grad_workspace_bytes(det, n_poses))
+        return fail(DRR_ENOMEM, "render_ncc_grad: workspace too small");
+    hipStream_t s = as_stream(stream);
+    st = launch_flat<kNcc>(packed, *vol, *det, poses, n_poses, image, nullptr, nullptr, target,
+                           target_stride, (double*)workspace, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_ncc_grad_finalize, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                       (const double*)workspace, flat_grid(*det).wg_per_pose, (double)hw, loss,
+                       grad_pose);
+    return check_launch("ncc_grad_finalize");
+}
+
+int32_t drr_pose_momentum_step(float* poses, float* velocity, const float* grad_pose,
+                               const float* rate, float momentum, int32_t n_poses, void* stream)
+{
+    if (n_poses < 0) return fail(DRR_EINVAL, "n_poses must be >= 0");
+    if (!isfinite(momentum)) return fail(DRR_EINVAL, "momentum must be finite");
+    if (n_poses == 0) return DRR_OK;
+    if (!poses || !velocity || !grad_pose || !rate)
+        return fail(DRR_EINVAL, "pose_momentum_step: NULL pointer");
+    const int n = n_poses * 7;
+    hipLaunchKernelGGL(k_momentum, dim3((n + 255) / 256), dim3(256), 0, as_stream(stream), poses,
+                       velocity, grad_pose, rate, momentum, n);
+    return check_launch("pose_momentum_step");
+}
+
+}  // extern "C"

@@ -1,0 +1,539 @@
+// Batched render plans: heterogeneous work items (volume, detector, pose,
+// outputs) rendered by persistent kernels that pull ray tiles from device
+// queues, optionally replayed from captured HIP graphs, with the launch
+// shape chosen by timing candidates (autotuner).
+//
+// Queues.  Each execute call groups its items by output mode (image /
+// image + counts / image + Jacobian) and lays the tiles of each group out
+// item after item.  The tile range of a group is split into 8 contiguous
+// shares, one per XCD; a workgroup first drains the share of the XCD it
+// runs on (hardware dispatch is round-robin over the XCDs), so concurrently
+// running workgroups of one XCD render neighbouring tiles of one pose and
+// share that XCD's L2, and then helps the other shares.  The counters are
+// reset by a small kernel at the start of every execute (no memset nodes in
+// the graph).  Which workgroup renders a tile never changes a result: tiles
+// are independent and each writes only its own pixels.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "render_kernels.hpp"
+
+namespace drr {
+
+constexpr int kPlanModes = 3;   // kImage, kCount, kJac
+constexpr int kXcds = 8;
+constexpr int kRing = 4;        // item tables in flight
+constexpr int kMaxPlanItems = 8192;
+
+struct PlanItem {
+    VolArgs vol;
+    DetArgs det;
+    const float* pose;
+    float* image;
+    float* jac;
+    int32_t* counts;
+    int32_t tiles_x;
+    int32_t tile_begin;   // first tile of this item within its group
+    int32_t pad[2];
+};
+
+struct PlanHeader {
+    int32_t first[kPlanModes];   // first item of each group
+    int32_t count[kPlanModes];   // items per group
+    int32_t tiles[kPlanModes];   // tiles per group
+    int32_t pad;
+};
+
+struct Slot {
+    PlanHeader* h_header = nullptr;   // pinned: header followed by items
+    PlanItem* h_items = nullptr;
+    char* d_block = nullptr;          // device copy of header + items
+    int32_t* d_counters = nullptr;    // [kPlanModes][kXcds]
+    hipEvent_t done = nullptr;
+    bool used = false;
+    std::map<int, hipGraphExec_t> graphs;   // by mode mask
+};
+
+// ------------------------------------------------------------------ kernels
+
+__global__ void k_reset_counters(int32_t* c, int n)
+{
+    if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+// Next tile of group `g` for a workgroup on XCD `xcd`, or -1 when drained.
+__device__ inline int next_tile(int32_t* counters, int total, int xcd, int* scan)
+{
+    while (*scan < kXcds) {
+        const int q = (xcd + *scan) % kXcds;
+        const int lo = (int)(((int64_t)total * q) / kXcds);
+        const int hi = (int)(((int64_t)total * (q + 1)) / kXcds);
+        const int t = atomicAdd(&counters[q], 1);
+        if (lo + t < hi) return lo + t;
+        ++*scan;
+    }
+    return -1;
+}
+
+template <int TW, int WX, int WY, int MODE>
+__global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* block,
+                                                                  int32_t* counters, int group)
+{
+    using S = TileShape<TW, WX, WY>;
+    __shared__ int s_tile;
+    __shared__ double lds[1];
+    const PlanHeader* hdr = (const PlanHeader*)block;
+    const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
+    const int first = hdr->first[group], count = hdr->count[group], total = hdr->tiles[group];
+    int32_t* ctr = counters + group * kXcds;
+    const int xcd = (int)(blockIdx.x % kXcds);
+    int scan = 0;
+    for (;;) {
+        if (threadIdx.x == 0) s_tile = next_tile(ctr, total, xcd, &scan);
+        __syncthreads();
+        const int t = s_tile;
+        __syncthreads();
+        if (t < 0) break;
+        // binary search: last item with tile_begin <= t
+        int lo = 0, hi = count - 1;
+        while (lo < hi) {
+            const int mid = (lo + hi + 1) >> 1;
+            if (items[first + mid].tile_begin <= t) lo = mid;
+            else hi = mid - 1;
+        }
+        const PlanItem& it = items[first + lo];
+        const int local = t - it.tile_begin;
+        const int ty = local / it.tiles_x, tx = local % it.tiles_x;
+        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(it.vol);
+        TileOut o;
+        o.image = it.image;
+        o.jac = it.jac;
+        o.counts = it.counts;
+        o.aux = nullptr;
+        o.partial = nullptr;
+        render_tile<TW, WX, WY, MODE>(it.vol, rsrc, it.det, it.pose, tx, ty, o, lds);
+    }
+    (void)sizeof(S);
+}
+
+// ------------------------------------------------------------------ shapes
+
+// Candidate launch shapes: wave tile width (pixels) and waves per workgroup.
+struct ShapeInfo {
+    int tw, wx, wy;
+};
+static const ShapeInfo kShapes[] = {
+    {8, 2, 2},    // 0: 16 x 16 px, 8 x 8 wave tiles
+    {8, 1, 1},    // 1:  8 x  8 px
+    {8, 1, 4},    // 2:  8 x 32 px
+    {16, 1, 4},   // 3: 16 x 16 px, 16 x 4 wave tiles
+    {4, 4, 1},    // 4: 16 x 16 px,  4 x 16 wave tiles
+    {8, 4, 1},    // 5: 32 x  8 px
+};
+constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
+
+typedef void (*PersistentFn)(const char*, int32_t*, int);
+
+template <int MODE>
+static PersistentFn persistent_fn(int code)
+{
+    switch (code) {
+    case 0: return render_persistent<8, 2, 2, MODE>;
+    case 1: return render_persistent<8, 1, 1, MODE>;
+    case 2: return render_persistent<8, 1, 4, MODE>;
+    case 3: return render_persistent<16, 1, 4, MODE>;
+    case 4: return render_persistent<4, 4, 1, MODE>;
+    default: return render_persistent<8, 4, 1, MODE>;
+    }
+}
+
+static PersistentFn kernel_for(int mode, int code)
+{
+    if (mode == kImage) return persistent_fn<kImage>(code);
+    if (mode == kCount) return persistent_fn<kCount>(code);
+    return persistent_fn<kJac>(code);
+}
+
+static int mode_of_flags(int32_t flags)
+{
+    if (flags & DRR_ITEM_JAC) return kJac;
+    if (flags & DRR_ITEM_COUNT) return kCount;
+    return kImage;
+}
+
+}  // namespace drr
+
+using namespace drr;
+
+struct drr_plan {
+    int max_items = 0;
+    std::vector<drr_volume_desc> vols;
+    std::vector<const void*> packed;
+    int tile_code = 0;
+    int wg_per_cu = 0;         // requested workgroups per CU (0 = occupancy limit)
+    int grid[kPlanModes] = {0, 0, 0};
+    int num_cus = 0;
+    bool use_graph = false;
+    Slot slots[kRing];
+    int next = 0;
+    std::mutex mu;
+};
+
+namespace drr {
+
+static size_t table_bytes(int max_items)
+{
+    return sizeof(PlanHeader) + (size_t)max_items * sizeof(PlanItem);
+}
+
+static int32_t compute_grids(drr_plan* p)
+{
+    const ShapeInfo& sh = kShapes[p->tile_code];
+    const int threads = 64 * sh.wx * sh.wy;
+    for (int m = 0; m < kPlanModes; ++m) {
+        int occ = 0;
+        hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(
+            &occ, (const void*)kernel_for(m, p->tile_code), threads, 0);
+        if (e != hipSuccess || occ < 1)
+            return fail(DRR_EHIP, "occupancy query failed: %s", hipGetErrorString(e));
+        int per = p->wg_per_cu > 0 && p->wg_per_cu < occ ? p->wg_per_cu : occ;
+        p->grid[m] = per * p->num_cus;
+        // whole multiples of the XCD count keep the XCD shares balanced
+        p->grid[m] = ((p->grid[m] + kXcds - 1) / kXcds) * kXcds;
+    }
+    return DRR_OK;
+}
+
+// Fills slot `s` for the given items; returns the mode mask via *mask.
+static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int n, int* mask)
+{
+    const ShapeInfo& sh = kShapes[p->tile_code];
+    const int pxw = sh.tw * sh.wx, pxh = (64 / sh.tw) * sh.wy;
+    PlanHeader* h = s.h_header;
+    int pos = 0;
+    *mask = 0;
+    for (int m = 0; m < kPlanModes; ++m) {
+        h->first[m] = pos;
+        h->count[m] = 0;
+        int64_t tiles = 0;
+        for (int i = 0; i < n; ++i) {
+            const drr_work_item& w = items[i];
+            if (mode_of_flags(w.flags) != m) continue;
+            PlanItem& it = s.h_items[pos++];
+            it.vol = vol_args(p->packed[w.volume], p->vols[w.volume]);
+            it.det = det_args(w.det);
+            it.pose = w.pose;
+            it.image = w.image;
+            it.jac = w.jac;
+            it.counts = w.counts;
+            it.tiles_x = (w.det.width + pxw - 1) / pxw;
+            const int ty = (w.det.height + pxh - 1) / pxh;
+            it.tile_begin = (int32_t)tiles;
+            tiles += (int64_t)it.tiles_x * ty;
+            h->count[m]++;
+        }
+        if (tiles > 0x7FFFFFFF) return fail(DRR_ENOTSUP, "too many tiles in one execute");
+        h->tiles[m] = (int32_t)tiles;
+        if (tiles > 0) *mask |= 1 << m;
+    }
+    return DRR_OK;
+}
+
+static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
+{
+    const ShapeInfo& sh = kShapes[p->tile_code];
+    const int threads = 64 * sh.wx * sh.wy;
+    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, s.d_counters,
+                       kPlanModes * kXcds);
+    int32_t rc = check_launch("plan counter reset");
+    if (rc) return rc;
+    for (int m = 0; m < kPlanModes; ++m) {
+        if (!(mask & (1 << m))) continue;
+        hipLaunchKernelGGL(kernel_for(m, p->tile_code), dim3(p->grid[m]), dim3(threads), 0, st,
+                           (const char*)s.d_block, s.d_counters, m);
+        if ((rc = check_launch("plan persistent kernel"))) return rc;
+    }
+    return DRR_OK;
+}
+
+static void drop_graphs(Slot& s)
+{
+    for (auto& kv : s.graphs) hipGraphExecDestroy(kv.second);
+    s.graphs.clear();
+}
+
+static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hipStream_t st)
+{
+    Slot& s = p->slots[p->next];
+    p->next = (p->next + 1) % kRing;
+    if (s.used) {
+        hipError_t e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return fail(DRR_EHIP, "plan slot wait: %s", hipGetErrorString(e));
+    }
+    int mask = 0;
+    int32_t rc = stage_items(p, s, items, n, &mask);
+    if (rc) return rc;
+    const size_t bytes = sizeof(PlanHeader) + (size_t)n * sizeof(PlanItem);
+    hipError_t e = hipMemcpyAsync(s.d_block, s.h_header, bytes, hipMemcpyHostToDevice, st);
+    if (e != hipSuccess) return fail(DRR_EHIP, "plan table copy: %s", hipGetErrorString(e));
+    if (p->use_graph && st != nullptr) {
+        auto found = s.graphs.find(mask);
+        if (found == s.graphs.end()) {
+            hipGraph_t g = nullptr;
+            hipGraphExec_t ge = nullptr;
+            e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+            if (e != hipSuccess) return fail(DRR_EHIP, "begin capture: %s", hipGetErrorString(e));
+            rc = enqueue_kernels(p, s, mask, st);
+            hipError_t e2 = hipStreamEndCapture(st, &g);
+            if (rc) return rc;
+            if (e2 != hipSuccess) return fail(DRR_EHIP, "end capture: %s", hipGetErrorString(e2));
+            e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
+            hipGraphDestroy(g);
+            if (e != hipSuccess) return fail(DRR_EHIP, "graph instantiate: %s", hipGetErrorString(e));
+            found = s.graphs.emplace(mask, ge).first;
+        }
+        e = hipGraphLaunch(found->second, st);
+        if (e != hipSuccess) return fail(DRR_EHIP, "graph launch: %s", hipGetErrorString(e));
+    } else {
+        rc = enqueue_kernels(p, s, mask, st);
+        if (rc) return rc;
+    }
+    e = hipEventRecord(s.done, st);
+    if (e != hipSuccess) return fail(DRR_EHIP, "plan event: %s", hipGetErrorString(e));
+    s.used = true;
+    return DRR_OK;
+}
+
+static int32_t validate_items(const drr_plan* p, const drr_work_item* items, int n)
+{
+    if (n < 0 || n > p->max_items)
+        return fail(DRR_EINVAL, "plan execute: %d items (capacity %d)", n, p->max_items);
+    if (n > 0 && !items) return fail(DRR_EINVAL, "plan execute: items is NULL");
+    for (int i = 0; i < n; ++i) {
+        const drr_work_item& w = items[i];
+        if (w.volume < 0 || w.volume >= (int)p->vols.size())
+            return fail(DRR_EINVAL, "item %d: volume index %d out of range", i, w.volume);
+        int32_t rc = validate_detector(&w.det);
+        if (rc) return rc;
+        if (!w.pose || !w.image) return fail(DRR_EINVAL, "item %d: NULL pose or image", i);
+        if ((w.flags & DRR_ITEM_JAC) && !w.jac) return fail(DRR_EINVAL, "item %d: NULL jac", i);
+        if ((w.flags & DRR_ITEM_COUNT) && !w.counts)
+            return fail(DRR_EINVAL, "item %d: NULL counts", i);
+        if ((w.flags & DRR_ITEM_JAC) && (w.flags & DRR_ITEM_COUNT))
+            return fail(DRR_EINVAL, "item %d: JAC and COUNT cannot be combined", i);
+    }
+    return DRR_OK;
+}
+
+// ------------------------------------------------------------------ autotune
+
+static std::string tune_key(const drr_plan* p, const drr_work_item* items, int n)
+{
+    std::string k = "v1";
+    for (const auto& v : p->vols) {
+        char b[96];
+        snprintf(b, sizeof b, "|%dx%dx%d@%.3g,%.3g,%.3g", v.nx, v.ny, v.nz, v.spacing[0],
+                 v.spacing[1], v.spacing[2]);
+        k += b;
+    }
+    int64_t px[kPlanModes] = {0, 0, 0};
+    for (int i = 0; i < n; ++i)
+        px[mode_of_flags(items[i].flags)] += (int64_t)items[i].det.height * items[i].det.width;
+    char b[96];
+    snprintf(b, sizeof b, "|n%d|px%lld,%lld,%lld", n, (long long)px[0], (long long)px[1],
+             (long long)px[2]);
+    return k + b;
+}
+
+static bool cache_lookup(const char* path, const std::string& key, int* code, int* wpc)
+{
+    if (!path) return false;
+    FILE* f = fopen(path, "r");
+    if (!f) return false;
+    char line[1024];
+    bool hit = false;
+    while (fgets(line, sizeof line, f)) {
+        char k[900];
+        int c, w;
+        if (sscanf(line, "%899s %d %d", k, &c, &w) == 3 && key == k && c >= 0 &&
+            c < kNumShapes && w >= 0) {
+            *code = c;
+            *wpc = w;
+            hit = true;
+        }
+    }
+    fclose(f);
+    return hit;
+}
+
+static void cache_store(const char* path, const std::string& key, int code, int wpc)
+{
+    if (!path) return;
+    FILE* f = fopen(path, "a");
+    if (!f) return;
+    fprintf(f, "%s %d %d\n", key.c_str(), code, wpc);
+    fclose(f);
+}
+
+static int32_t time_config(drr_plan* p, const drr_work_item* items, int n, hipStream_t st,
+                           float* ms)
+{
+    int32_t rc = compute_grids(p);
+    if (rc) return rc;
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    rc = execute_locked(p, items, n, st);   // warm-up (also captures the graph)
+    const int reps = 3;
+    hipEventRecord(a, st);
+    for (int r = 0; r < reps && rc == DRR_OK; ++r) rc = execute_locked(p, items, n, st);
+    hipEventRecord(b, st);
+    hipError_t e = hipEventSynchronize(b);
+    float t = 0.0f;
+    hipEventElapsedTime(&t, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    if (rc) return rc;
+    if (e != hipSuccess) return fail(DRR_EHIP, "autotune sync: %s", hipGetErrorString(e));
+    *ms = t / reps;
+    return DRR_OK;
+}
+
+static int32_t autotune(drr_plan* p, const drr_work_item* items, int n, hipStream_t st,
+                        const char* cache)
+{
+    const std::string key = tune_key(p, items, n);
+    int code = 0, wpc = 0;
+    if (cache_lookup(cache, key, &code, &wpc)) {
+        p->tile_code = code;
+        p->wg_per_cu = wpc;
+        return compute_grids(p);
+    }
+    float best = 1e30f;
+    int best_code = 0, best_wpc = 0;
+    const int wpcs[] = {0, 2};   // occupancy limit, or two workgroups per CU
+    for (int c = 0; c < kNumShapes; ++c) {
+        for (int w : wpcs) {
+            p->tile_code = c;
+            p->wg_per_cu = w;
+            for (Slot& s : p->slots) drop_graphs(s);
+            float ms = 0.0f;
+            int32_t rc = time_config(p, items, n, st, &ms);
+            if (rc) return rc;
+            if (ms < best) {
+                best = ms;
+                best_code = c;
+                best_wpc = w;
+            }
+        }
+    }
+    for (Slot& s : p->slots) drop_graphs(s);
+    p->tile_code = best_code;
+    p->wg_per_cu = best_wpc;
+    cache_store(cache, key, best_code, best_wpc);
+    return compute_grids(p);
+}
+
+static void free_plan(drr_plan* p)
+{
+    for (Slot& s : p->slots) {
+        if (s.used && s.done) hipEventSynchronize(s.done);
+        drop_graphs(s);
+        if (s.done) hipEventDestroy(s.done);
+        if (s.h_header) hipHostFree(s.h_header);
+        if (s.d_block) hipFree(s.d_block);
+        if (s.d_counters) hipFree(s.d_counters);
+    }
+    delete p;
+}
+
+}  // namespace drr
+
+extern "C" {
+
+int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_items,
+                        int32_t n_tune_items, void* stream, drr_plan** out)
+{
+    if (!desc || !out) return fail(DRR_EINVAL, "plan_create: NULL argument");
+    *out = nullptr;
+    if (desc->max_items < 1 || desc->max_items > kMaxPlanItems)
+        return fail(DRR_EINVAL, "plan_create: max_items must be in [1, %d]", kMaxPlanItems);
+    if (desc->n_volumes < 1 || !desc->volumes || !desc->packed)
+        return fail(DRR_EINVAL, "plan_create: need at least one volume");
+    drr_plan* p = new drr_plan();
+    p->max_items = desc->max_items;
+    p->use_graph = desc->use_graph != 0;
+    for (int v = 0; v < desc->n_volumes; ++v) {
+        int32_t rc = validate_volume(&desc->volumes[v]);
+        if (rc || !desc->packed[v]) {
+            delete p;
+            return rc ? rc : fail(DRR_EINVAL, "plan_create: packed[%d] is NULL", v);
+        }
+        p->vols.push_back(desc->volumes[v]);
+        p->packed.push_back(desc->packed[v]);
+    }
+    int dev = 0;
+    hipGetDevice(&dev);
+    hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (p->num_cus < 1) p->num_cus = 1;
+    const size_t tb = table_bytes(p->max_items);
+    for (Slot& s : p->slots) {
+        if (hipHostMalloc((void**)&s.h_header, tb, hipHostMallocDefault) != hipSuccess ||
+            hipMalloc((void**)&s.d_block, tb) != hipSuccess ||
+            hipMalloc((void**)&s.d_counters, kPlanModes * kXcds * sizeof(int32_t)) !=
+                hipSuccess ||
+            hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess) {
+            free_plan(p);
+            return fail(DRR_ENOMEM, "plan_create: allocation failed");
+        }
+        s.h_items = (PlanItem*)((char*)s.h_header + sizeof(PlanHeader));
+    }
+    int32_t rc = compute_grids(p);
+    if (rc == DRR_OK && desc->autotune) {
+        if (n_tune_items < 1 || !tune_items) {
+            rc = fail(DRR_EINVAL, "plan_create: autotune needs sample items");
+        } else if ((rc = validate_items(p, tune_items, n_tune_items)) == DRR_OK) {
+            rc = autotune(p, tune_items, n_tune_items, as_stream(stream), desc->tune_cache_path);
+        }
+    }
+    if (rc) {
+        free_plan(p);
+        return rc;
+    }
+    *out = p;
+    return DRR_OK;
+}
+
+int32_t drr_plan_execute(drr_plan* plan, const drr_work_item* items, int32_t n_items,
+                         void* stream)
+{
+    if (!plan) return fail(DRR_EINVAL, "plan_execute: NULL plan");
+    std::lock_guard<std::mutex> lock(plan->mu);
+    int32_t rc = validate_items(plan, items, n_items);
+    if (rc) return rc;
+    if (n_items == 0) return DRR_OK;
+    return execute_locked(plan, items, n_items, as_stream(stream));
+}
+
+int32_t drr_plan_config(const drr_plan* plan, int32_t* tile_code, int32_t* wg_per_cu,
+                        int32_t* use_graph)
+{
+    if (!plan) return fail(DRR_EINVAL, "plan_config: NULL plan");
+    if (tile_code) *tile_code = plan->tile_code;
+    if (wg_per_cu) *wg_per_cu = plan->wg_per_cu;
+    if (use_graph) *use_graph = plan->use_graph ? 1 : 0;
+    return DRR_OK;
+}
+
+void drr_plan_destroy(drr_plan* plan)
+{
+    if (plan) free_plan(plan);
+}
+
+}  // extern "C"

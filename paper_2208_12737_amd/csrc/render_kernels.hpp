@@ -1,0 +1,171 @@
+// Render kernels: one workgroup renders one tile of one pose's detector.
+//
+// A wave covers a TW x (64/TW) block of pixels, one ray per lane; a
+// workgroup is WX x WY waves.  Neighbouring lanes trace neighbouring rays,
+// so at any step the wave's gathers fall in a compact footprint of the
+// volume and share cache lines.
+//
+// Modes
+//   kImage    image only
+//   kCount    image + per-pixel count of positive-length segments (gathers)
+//   kJac      image + per-pixel Jacobian d image / d pose (7 floats)
+//   kRetrace  sum over the tile of g * Jacobian (g = upstream image gradient)
+//   kNcc      image (optional) + per-tile sums for the ZNCC loss and its
+//             pose gradient: I, I^2, T, T^2, IT, J[7], T J[7], I J[7]
+#pragma once
+
+#include "siddon.hpp"
+
+namespace drr {
+
+enum Mode { kImage = 0, kCount = 1, kJac = 2, kRetrace = 3, kNcc = 4 };
+
+constexpr int kNccSums = 26;
+
+template <int MODE>
+struct ModeTraits {
+    static constexpr bool jac = MODE == kJac || MODE == kRetrace || MODE == kNcc;
+    static constexpr bool count = MODE == kCount;
+    static constexpr int nsum = MODE == kRetrace ? 7 : (MODE == kNcc ? kNccSums : 0);
+};
+
+// Per-tile outputs.  `aux` is the upstream image gradient (kRetrace) or the
+// target image (kNcc) of this pose; `partial` receives the tile's sums.
+struct TileOut {
+    float* image;      // [H][W] of this pose, may be NULL in kRetrace/kNcc
+    float* jac;        // [H][W][7]
+    int32_t* counts;   // [H][W]
+    const float* aux;  // [H][W]
+    double* partial;   // nsum doubles
+};
+
+template <int TW, int WX, int WY>
+struct TileShape {
+    static constexpr int th = 64 / TW;
+    static constexpr int px_w = TW * WX;   // pixels per workgroup tile, along w
+    static constexpr int px_h = th * WY;   // along h
+    static constexpr int threads = 64 * WX * WY;
+};
+
+// Fixed-order workgroup reduction of NS per-lane values into out[0..NS).
+template <int NS, int NWAVES>
+__device__ inline void block_sums(double (&vals)[NS], double* lds, double* out)
+{
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+#pragma unroll
+    for (int k = 0; k < NS; ++k) {
+        double s = wave_sum(vals[k]);
+        if (lane == 0) lds[wave * NS + k] = s;
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < NS) {
+        double acc = 0.0;
+        for (int wv = 0; wv < NWAVES; ++wv) acc += lds[wv * NS + threadIdx.x];
+        out[threadIdx.x] = acc;
+    }
+    __syncthreads();
+}
+
+template <int TW, int WX, int WY, int MODE>
+__device__ inline void render_tile(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
+                                   const DetArgs& D, const float* __restrict__ pose, int tx,
+                                   int ty, const TileOut& o, double* lds)
+{
+    using S = TileShape<TW, WX, WY>;
+    using T = ModeTraits<MODE>;
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int wx = wave % WX, wy = wave / WX;
+    const int w = (tx * WX + wx) * TW + lane % TW;
+    const int h = (ty * WY + wy) * S::th + lane / TW;
+    const bool inside = (w < D.W) && (h < D.H);
+
+    const PoseTrig q = pose_trig(pose);
+    const Mat3 R = rotation(q.ct, q.st, q.cp, q.sp, q.cg, q.sg, -1);
+    const double u = ((double)w + 0.5 - 0.5 * (double)D.W) * (double)D.dx;
+    const double v = ((double)h + 0.5 - 0.5 * (double)D.H) * (double)D.dy;
+    double s[3], d[3];
+    ray_of(q, R, u, v, s, d);
+
+    RayAcc r;
+    r.sum = 0.0;
+    r.amin = 0.0;
+    r.a0 = r.a1 = r.b0 = r.b1 = r.a_none = r.b_none = 0.0f;
+    r.nseg = 0;
+    r.valid = true;
+    if (inside) r = trace<T::jac, T::count>(V, rsrc, s, d);
+
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const float E = r.valid ? (float)(L * r.sum) : __builtin_nanf("");
+    const int64_t pix = (int64_t)h * D.W + w;
+
+    float J[7];
+    if (T::jac) {
+        if (inside && r.valid) {
+            ray_jacobian(r, q, R, u, v, d, J);
+        } else {
+#pragma unroll
+            for (int j = 0; j < 7; ++j) J[j] = inside ? __builtin_nanf("") : 0.0f;
+        }
+    }
+
+    if (inside) {
+        if (o.image) o.image[pix] = E;
+        if (MODE == kCount) o.counts[pix] = r.nseg;
+        if (MODE == kJac) {
+#pragma unroll
+            for (int j = 0; j < 7; ++j) o.jac[pix * 7 + j] = J[j];
+        }
+    }
+
+    if (MODE == kRetrace) {
+        const float g = inside ? o.aux[pix] : 0.0f;
+        double vals[7];
+#pragma unroll
+        for (int j = 0; j < 7; ++j) vals[j] = inside ? (double)g * (double)J[j] : 0.0;
+        block_sums<7, WX * WY>(vals, lds, o.partial);
+    }
+    if (MODE == kNcc) {
+        const double I = inside ? (double)E : 0.0;
+        const double Tv = inside ? (double)o.aux[pix] : 0.0;
+        double vals[kNccSums];
+        vals[0] = I;
+        vals[1] = I * I;
+        vals[2] = Tv;
+        vals[3] = Tv * Tv;
+        vals[4] = I * Tv;
+#pragma unroll
+        for (int j = 0; j < 7; ++j) {
+            const double Jj = inside ? (double)J[j] : 0.0;
+            vals[5 + j] = Jj;
+            vals[12 + j] = Tv * Jj;
+            vals[19 + j] = I * Jj;
+        }
+        block_sums<kNccSums, WX * WY>(vals, lds, o.partial);
+    }
+}
+
+// Flat launch: grid = wg_per_pose * n_poses workgroups, XCD-aware ordering.
+template <int TW, int WX, int WY, int MODE>
+__global__ __launch_bounds__(64 * WX * WY) void render_flat(
+    VolArgs V, DetArgs D, const float* __restrict__ poses, int tiles_x, int wg_per_pose,
+    float* image, float* jac, int32_t* counts, const float* aux, int64_t aux_stride,
+    double* partials)
+{
+    using T = ModeTraits<MODE>;
+    __shared__ double lds[(T::nsum > 0 ? T::nsum : 1) * WX * WY];
+    const uint32_t logical = xcd_logical(blockIdx.x, gridDim.x);
+    const int b = (int)(logical / (uint32_t)wg_per_pose);
+    const int t = (int)(logical % (uint32_t)wg_per_pose);
+    const int ty = t / tiles_x, tx = t % tiles_x;
+    const int64_t hw = (int64_t)D.H * D.W;
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(V);
+    TileOut o;
+    o.image = image ? image + b * hw : nullptr;
+    o.jac = jac ? jac + b * hw * 7 : nullptr;
+    o.counts = counts ? counts + b * hw : nullptr;
+    o.aux = aux ? aux + b * aux_stride : nullptr;
+    o.partial = T::nsum > 0 ? partials + ((int64_t)b * wg_per_pose + t) * T::nsum : nullptr;
+    render_tile<TW, WX, WY, MODE>(V, rsrc, D, poses + 7 * b, tx, ty, o, lds);
+}
+
+}  // namespace drr

@@ -1,0 +1,380 @@
+// Device-side Siddon-Jacobs ray traversal for gfx950.
+//
+// One ray per lane.  The plane crossings of Eq. 3 are produced in increasing
+// order by a three-way merge kept in registers (the iterative form of
+// Sec. 2.2): each axis holds the parameter of its next crossing and the
+// parametric step between its planes; the smallest of the three ends the
+// current segment (Eq. 2), and the axes that attain it advance.  Crossing
+// state is FP64 so that segment lengths, taken as differences of crossing
+// parameters, keep their relative accuracy; voxel values are FP32 and the
+// path sum is accumulated in FP64.
+//
+// The packed volume is the caller's grid surrounded by a one-voxel border
+// of zeros, read through a raw buffer resource: a rounding-induced step one
+// voxel past the last crossing lands in the border (value 0), and any offset
+// beyond the buffer reads 0 instead of faulting.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace drr {
+
+constexpr uint32_t kBufferDword3 = 0x00020000u;  // gfx9 raw buffer, 32-bit data
+
+// Crossing parameters are advanced by repeated addition, so a plane that
+// coincides with the exit (or with another plane) can land a few ulps away
+// from it and open a sliver segment.  The segment counter (gathers per ray)
+// ignores segments shorter than this many units of alpha -- 2^-36 of the
+// source-detector distance, about 1.5e-8 mm at 1 m.  The path sum itself
+// always includes every segment.
+constexpr double kSliver = 0x1p-36;
+
+struct VolArgs {
+    const float* packed;
+    double spacing[3];
+    double origin[3];
+    int32_t n[3];
+    uint32_t bytes;  // size of the packed buffer
+};
+
+struct DetArgs {
+    double dx, dy;
+    int32_t H, W;
+};
+
+// ------------------------------------------------------------------ geometry
+
+struct Mat3 {
+    double m[3][3];
+};
+
+__device__ inline Mat3 mul(const Mat3& a, const Mat3& b)
+{
+    Mat3 c;
+#pragma unroll
+    for (int i = 0; i < 3; ++i)
+#pragma unroll
+        for (int j = 0; j < 3; ++j)
+            c.m[i][j] = a.m[i][0] * b.m[0][j] + a.m[i][1] * b.m[1][j] + a.m[i][2] * b.m[2][j];
+    return c;
+}
+
+// Rz(theta) Ry(phi) Rx(gamma); `which` = 0/1/2 differentiates one factor.
+__device__ inline Mat3 rotation(double ct, double st, double cp, double sp, double cg, double sg,
+                                int which)
+{
+    Mat3 z = {{{ct, -st, 0.0}, {st, ct, 0.0}, {0.0, 0.0, 1.0}}};
+    Mat3 y = {{{cp, 0.0, sp}, {0.0, 1.0, 0.0}, {-sp, 0.0, cp}}};
+    Mat3 x = {{{1.0, 0.0, 0.0}, {0.0, cg, -sg}, {0.0, sg, cg}}};
+    if (which == 0) z = Mat3{{{-st, -ct, 0.0}, {ct, -st, 0.0}, {0.0, 0.0, 0.0}}};
+    if (which == 1) y = Mat3{{{-sp, 0.0, cp}, {0.0, 0.0, 0.0}, {-cp, 0.0, -sp}}};
+    if (which == 2) x = Mat3{{{0.0, 0.0, 0.0}, {0.0, -sg, -cg}, {0.0, cg, -sg}}};
+    return mul(mul(z, y), x);
+}
+
+struct PoseTrig {
+    double ct, st, cp, sp, cg, sg;
+    double rho;
+    double t[3];
+};
+
+__device__ inline PoseTrig pose_trig(const float* __restrict__ pose)
+{
+    PoseTrig q;
+    sincos((double)pose[0], &q.st, &q.ct);
+    sincos((double)pose[1], &q.sp, &q.cp);
+    sincos((double)pose[2], &q.sg, &q.cg);
+    q.t[0] = pose[3];
+    q.t[1] = pose[4];
+    q.t[2] = pose[5];
+    q.rho = 0.5 * (double)pose[6];
+    return q;
+}
+
+// Source s and direction d = p - s for detector coordinates (u, v).
+__device__ inline void ray_of(const PoseTrig& q, const Mat3& R, double u, double v, double s[3],
+                              double d[3])
+{
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        s[c] = q.rho * R.m[c][0] + q.t[c];
+        d[c] = -2.0 * q.rho * R.m[c][0] + u * R.m[c][1] + v * R.m[c][2];
+    }
+}
+
+// ------------------------------------------------------------------ traversal
+
+// Per-ray result.  sum = E / |d|.  For the Jacobian, crossings are grouped by
+// the axis of their plane: A_c = sum of (V_before - V_after) over the c-plane
+// crossings, B_c = sum of (alpha - alpha_min)(V_before - V_after); only x and
+// y are accumulated -- z follows from sum_k (V_before - V_after) = 0 and
+// sum_k (alpha_k - alpha_min)(V_before - V_after) = E/|d| over all
+// crossings.  Ends clamped to the ray's own [0, 1] do not move with the pose
+// and are kept apart in a_none / b_none.
+struct RayAcc {
+    double sum;
+    double amin;
+    float a0, a1, b0, b1, a_none, b_none;
+    int32_t nseg;
+    bool valid;  // false: non-finite geometry (result NaN)
+};
+
+// Volume value at a byte offset into the packed buffer (0 beyond its end).
+__device__ inline float ld(const __amdgpu_buffer_rsrc_t& r, uint32_t byte_off)
+{
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+
+// min of two non-NaN doubles.  fmin() would first quiet possible signalling
+// NaNs of loop-carried operands (an extra instruction per operand); the
+// crossing parameters are never NaN (non-finite rays are rejected before
+// the loop), so the bare instruction is exact here.
+__device__ inline double min_nn(double a, double b)
+{
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+template <bool JAC, bool COUNT>
+__device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
+                               const double s[3], const double d[3])
+{
+    RayAcc r;
+    r.sum = 0.0;
+    r.amin = 0.0;
+    r.a0 = r.a1 = r.b0 = r.b1 = r.a_none = r.b_none = 0.0f;
+    r.nseg = 0;
+    r.valid = true;
+
+    bool finite = true;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) finite = finite && isfinite(s[c]) && isfinite(d[c]);
+    if (!finite) {
+        r.valid = false;
+        return r;
+    }
+
+    // Entry and exit parameters (Sec. 2.3), clamped to [0, 1].
+    double amin = 0.0, amax = 1.0;
+    int amin_ax = -1, amax_ax = -1;
+    bool miss = false;
+    double o[3], sp[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        o[c] = V.origin[c];
+        sp[c] = V.spacing[c];
+        double hi_plane = o[c] + (double)V.n[c] * sp[c];
+        if (d[c] != 0.0) {
+            double a0 = (o[c] - s[c]) / d[c];
+            double a1 = (hi_plane - s[c]) / d[c];
+            double lo = fmin(a0, a1), hi = fmax(a0, a1);
+            if (lo > amin) {
+                amin = lo;
+                amin_ax = c;
+            }
+            if (hi < amax) {
+                amax = hi;
+                amax_ax = c;
+            }
+        } else if (!(s[c] >= o[c] && s[c] < hi_plane)) {
+            miss = true;
+        }
+    }
+    r.amin = amin;
+    if (miss || !(amin < amax)) return r;
+
+    // Voxel just past the entry, and each axis's first crossing after it.
+    const double ae = amin + (amax - amin) * 0x1p-30;
+    const int32_t pitch_y = V.n[2] + 2;
+    const int32_t pitch_x = (V.n[1] + 2) * pitch_y;
+    const int32_t pitch[3] = {pitch_x * 4, pitch_y * 4, 4};   // bytes
+    double an[3], da[3];
+    int32_t stride[3];
+    uint32_t off = 0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double f = floor((s[c] + ae * d[c] - o[c]) / sp[c]);
+        int32_t i = (int32_t)fmin(fmax(f, 0.0), (double)(V.n[c] - 1));
+        off += (uint32_t)((i + 1) * pitch[c]);
+        if (d[c] > 0.0) {
+            an[c] = (o[c] + (double)(i + 1) * sp[c] - s[c]) / d[c];
+            da[c] = sp[c] / d[c];
+            stride[c] = pitch[c];
+        } else if (d[c] < 0.0) {
+            an[c] = (o[c] + (double)i * sp[c] - s[c]) / d[c];
+            da[c] = -sp[c] / d[c];
+            stride[c] = -pitch[c];
+        } else {
+            an[c] = __builtin_inf();
+            da[c] = 0.0;
+            stride[c] = 0;
+        }
+    }
+
+    double ax = an[0], ay = an[1], az = an[2];
+    double acc = 0.0;
+    int32_t nseg = 0;
+    float vprev = 0.0f;
+    int idprev = amin_ax;  // axis of the crossing that starts the segment
+    float A0 = 0.f, A1 = 0.f, B0 = 0.f, B1 = 0.f, An = 0.f, Bn = 0.f;
+
+    // One merge step: close the segment [a_start, next crossing] in the
+    // current voxel (value vc), advance the winning axes and issue the load
+    // of the next voxel into vn.  The loop below alternates the roles of
+    // (v0, a0) and (v1, a1) so that no register copy forces an early wait on
+    // the load: its latency overlaps the next step's merge arithmetic.
+    auto step = [&](const float vc, float& vn, const double a_start, double& a_end) {
+        const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));
+        const bool bx = ax == anext, by = ay == anext, bz = az == anext;
+        ax = bx ? ax + da[0] : ax;
+        ay = by ? ay + da[1] : ay;
+        az = bz ? az + da[2] : az;
+        off += (bx ? (uint32_t)stride[0] : 0u) + (by ? (uint32_t)stride[1] : 0u) +
+               (bz ? (uint32_t)stride[2] : 0u);
+        vn = ld(rsrc, off);
+        const double seg = anext - a_start;
+        acc = fma(seg, (double)vc, acc);
+        if (COUNT) nseg += seg > kSliver ? 1 : 0;
+        if (JAC) {
+            // crossing at a_start: V_before = vprev, V_after = vc.  A step
+            // taken after the ray has ended (a_start == amax) is empty.
+            const bool live = a_start < amax;
+            const float dl = live ? vprev - vc : 0.0f;
+            const float t = (float)(a_start - amin);
+            A0 += idprev == 0 ? dl : 0.0f;
+            B0 += idprev == 0 ? t * dl : 0.0f;
+            A1 += idprev == 1 ? dl : 0.0f;
+            B1 += idprev == 1 ? t * dl : 0.0f;
+            An += idprev < 0 ? dl : 0.0f;
+            Bn += idprev < 0 ? t * dl : 0.0f;
+            vprev = live ? vc : vprev;
+            idprev = bx ? 0 : (by ? 1 : 2);
+        }
+        a_end = anext;
+    };
+
+    float v0 = ld(rsrc, off), v1 = 0.0f;
+    double a0 = amin, a1 = amin;
+    bool active = true;
+    // Every crossing either ends the ray or advances an axis by one plane,
+    // so n_x + n_y + n_z + 4 steps bound the loop for any input.  The loop
+    // is wave-uniform; lanes that finished idle under the exec mask.
+    const int cap = (V.n[0] + V.n[1] + V.n[2] + 5) / 2;
+    // Both steps of an iteration always run for a live lane: when the first
+    // one ends the ray, the second sees every axis at or beyond amax and
+    // closes an empty segment (seg = 0).  Keeping the second step
+    // unconditional keeps the first step's load ahead of its use.
+    for (int it = 0; it < cap; ++it) {
+        if (active) {
+            step(v0, v1, a0, a1);
+            step(v1, v0, a1, a0);
+            active = a0 < amax;
+        }
+        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+    }
+    if (JAC) {
+        // exit crossing at amax: V_before = last voxel, V_after = 0
+        const float t = (float)(amax - amin);
+        if (amax_ax == 0) {
+            A0 += vprev;
+            B0 += t * vprev;
+        } else if (amax_ax == 1) {
+            A1 += vprev;
+            B1 += t * vprev;
+        } else if (amax_ax < 0) {
+            An += vprev;
+            Bn += t * vprev;
+        }
+    }
+    r.sum = acc;
+    r.nseg = nseg;
+    r.a0 = A0;
+    r.a1 = A1;
+    r.b0 = B0;
+    r.b1 = B1;
+    r.a_none = An;
+    r.b_none = Bn;
+    return r;
+}
+
+// d E / d pose for one ray from its traversal sums (frozen voxel indices).
+//   E = L * sum_k alpha_k (V_{k-1} - V_k),  alpha_k = (q_k - s_c) / d_c,
+//   d alpha_k = -(s'_c + alpha_k d'_c) / d_c,  d L = dhat . d'
+//   => dE = g_d . d' + g_s . s'  with  g_s = -L A / d,
+//      g_d = sum * d / L - L B / d   (per axis c; axes with d_c = 0 drop out)
+// The pose enters through s' and d' = p' - s':
+//   angle j:  s' = rho dR_j e_x,   d' = dR_j (-2 rho, u, v)
+//   t_c:      s' = e_c,            d' = 0
+//   sdd:      s' = R e_x / 2,      d' = -R e_x
+__device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, const Mat3& R,
+                                    double u, double v, const double d[3], float J[7])
+{
+    double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    double A[3], B[3];
+    A[0] = r.a0;
+    A[1] = r.a1;
+    A[2] = -((double)r.a0 + (double)r.a1 + (double)r.a_none);
+    B[0] = r.b0;
+    B[1] = r.b1;
+    B[2] = r.sum - (double)r.b0 - (double)r.b1 - (double)r.b_none;
+    double gs[3], gd[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c) {
+        double Bc = B[c] + r.amin * A[c];
+        if (d[c] != 0.0) {
+            gs[c] = -L * A[c] / d[c];
+            gd[c] = r.sum * d[c] / L - L * Bc / d[c];
+        } else {
+            gs[c] = 0.0;
+            gd[c] = 0.0;
+        }
+    }
+    const double cv[3] = {-2.0 * q.rho, u, v};
+#pragma unroll
+    for (int j = 0; j < 3; ++j) {
+        Mat3 dR = rotation(q.ct, q.st, q.cp, q.sp, q.cg, q.sg, j);
+        double acc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 3; ++c) {
+            double dd = dR.m[c][0] * cv[0] + dR.m[c][1] * cv[1] + dR.m[c][2] * cv[2];
+            acc += gd[c] * dd + gs[c] * q.rho * dR.m[c][0];
+        }
+        J[j] = (float)acc;
+    }
+    J[3] = (float)gs[0];
+    J[4] = (float)gs[1];
+    J[5] = (float)gs[2];
+    double js = 0.0;
+#pragma unroll
+    for (int c = 0; c < 3; ++c) js += (0.5 * gs[c] - gd[c]) * R.m[c][0];
+    J[6] = (float)js;
+}
+
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const VolArgs& V)
+{
+    return __builtin_amdgcn_make_buffer_rsrc((void*)V.packed, (short)0, (int)V.bytes,
+                                             (int)kBufferDword3);
+}
+
+// Maps the hardware workgroup id to a logical one so that the workgroups
+// that land on one XCD (dispatch is round-robin over the 8 XCDs) take a
+// contiguous range of logical ids, i.e. neighbouring tiles of one pose.
+__device__ inline uint32_t xcd_logical(uint32_t bid, uint32_t total)
+{
+    const uint32_t per = total / 8u, rem = total % 8u;
+    const uint32_t xcd = bid % 8u, local = bid / 8u;
+    return xcd < rem ? xcd * (per + 1u) + local : rem * (per + 1u) + (xcd - rem) * per + local;
+}
+
+// ------------------------------------------------------------------ reductions
+
+__device__ inline double wave_sum(double x)
+{
+#pragma unroll
+    for (int o = 32; o >= 1; o >>= 1) x += __shfl_xor(x, o, 64);
+    return x;
+}
+
+}  // namespace drr

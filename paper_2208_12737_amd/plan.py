@@ -1,0 +1,106 @@
+"""Batched render plans (persistent tile-queue kernels, HIP graph replay,
+autotuned launch shape) -- a thin wrapper of drr_plan_* in include/drr.h."""
+
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+from typing import Optional, Sequence
+
+import torch
+
+from . import _lib
+from .drr import Detector, Volume, _stream
+
+
+@dataclass
+class Item:
+    """One render: volume index, detector, a device pose [7] and outputs."""
+    volume: int
+    det: Detector
+    pose: torch.Tensor
+    image: torch.Tensor
+    jac: Optional[torch.Tensor] = None
+    counts: Optional[torch.Tensor] = None
+
+    def flags(self) -> int:
+        f = 0
+        if self.jac is not None:
+            f |= _lib.DRR_ITEM_JAC
+        if self.counts is not None:
+            f |= _lib.DRR_ITEM_COUNT
+        return f
+
+
+def _items_array(items: Sequence[Item]):
+    arr = (_lib.WorkItem * max(len(items), 1))()
+    for k, it in enumerate(items):
+        for t, name in ((it.pose, "pose"), (it.image, "image")):
+            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
+                raise TypeError(f"item {k}: {name} must be a contiguous float32 GPU tensor")
+        if it.image.numel() != it.det.pixels or it.pose.numel() != 7:
+            raise ValueError(f"item {k}: image or pose has the wrong size")
+        w = arr[k]
+        w.volume = it.volume
+        w.flags = it.flags()
+        w.det = it.det.desc
+        w.pose = it.pose.data_ptr()
+        w.image = it.image.data_ptr()
+        w.jac = it.jac.data_ptr() if it.jac is not None else None
+        w.counts = it.counts.data_ptr() if it.counts is not None else None
+    return arr
+
+
+class Plan:
+    """Renders lists of heterogeneous items in one persistent launch.
+
+    Results equal rendering each item alone.  `autotune` times candidate
+    launch shapes on `tune_items` at creation (results cached in
+    `cache_path` when given)."""
+
+    def __init__(self, volumes: Sequence[Volume], max_items: int = 1024, use_graph: bool = True,
+                 autotune: bool = False, tune_items: Optional[Sequence[Item]] = None,
+                 cache_path: Optional[str] = None):
+        self.volumes = list(volumes)
+        self._descs = (_lib.VolumeDesc * len(self.volumes))(*[v.desc for v in self.volumes])
+        self._packed = (ctypes.c_void_p * len(self.volumes))(
+            *[v.packed.data_ptr() for v in self.volumes])
+        d = _lib.PlanDesc()
+        d.max_items = max_items
+        d.n_volumes = len(self.volumes)
+        d.volumes = self._descs
+        d.packed = self._packed
+        d.use_graph = 1 if use_graph else 0
+        d.autotune = 1 if autotune else 0
+        self._cache = cache_path.encode() if cache_path else None
+        d.tune_cache_path = self._cache
+        self._desc = d
+        tune = list(tune_items or [])
+        arr = _items_array(tune) if tune else None
+        h = ctypes.c_void_p()
+        _lib.call("drr_plan_create", ctypes.byref(d), arr, len(tune), _stream(), ctypes.byref(h))
+        self._h = h
+        self.max_items = max_items
+
+    def execute(self, items: Sequence[Item]) -> None:
+        if len(items) == 0:
+            return
+        arr = _items_array(items)
+        _lib.call("drr_plan_execute", self._h, arr, len(items), _stream())
+
+    @property
+    def config(self):
+        t, w, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.call("drr_plan_config", self._h, ctypes.byref(t), ctypes.byref(w), ctypes.byref(g))
+        return {"tile_code": t.value, "wg_per_cu": w.value, "use_graph": bool(g.value)}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            _lib.load().drr_plan_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,93 @@
+"""Host-side checks of the C ABI: the library loads and exports every
+symbol include/drr.h declares, and argument validation rejects bad input
+before any device work (no GPU needed)."""
+
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_2208_12737_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    src = open(os.path.join(ROOT, "include", "drr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(drr_[a-z_]+)\s*\(", src)))
+
+
+def test_header_declares_expected_entry_points():
+    names = _declared_functions()
+    for n in ("drr_render", "drr_volume_pack", "drr_render_backward", "drr_ncc_forward",
+              "drr_plan_create", "drr_plan_execute"):
+        assert n in names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in _declared_functions():
+        assert hasattr(lib, name), name
+        assert name in _lib.SIGNATURES, f"binding lacks {name}"
+
+
+def test_version_and_status_strings():
+    lib = _lib.load()
+    assert lib.drr_version() >= 10000
+    assert lib.drr_status_string(0) == b"ok"
+    assert b"invalid" in lib.drr_status_string(_lib.DRR_EINVAL)
+
+
+def test_packed_bytes_includes_zero_border():
+    lib = _lib.load()
+    d = _lib.volume_desc((4, 5, 6), (1, 1, 1), (0, 0, 0))
+    assert lib.drr_volume_packed_bytes(ctypes.byref(d)) == 6 * 7 * 8 * 4
+
+
+@pytest.mark.parametrize("shape,spacing", [((0, 5, 6), (1, 1, 1)), ((4, 5, 6), (1, 0, 1)),
+                                           ((4, 5, 6), (1, float("nan"), 1))])
+def test_invalid_volume_rejected(shape, spacing):
+    lib = _lib.load()
+    d = _lib.volume_desc(shape, spacing, (0, 0, 0))
+    assert lib.drr_volume_packed_bytes(ctypes.byref(d)) == 0
+    st = lib.drr_volume_pack(None, None, ctypes.byref(d), None)
+    assert st == _lib.DRR_EINVAL
+    assert lib.drr_last_error()
+
+
+def test_render_validation_before_launch():
+    lib = _lib.load()
+    v = _lib.volume_desc((4, 4, 4), (1, 1, 1), (-2, -2, -2))
+    good = _lib.detector_desc(8, 8, 1.0, 1.0)
+    bad = _lib.detector_desc(0, 8, 1.0, 1.0)
+    assert lib.drr_render(None, ctypes.byref(v), ctypes.byref(bad), None, 1, None, None,
+                          None) == _lib.DRR_EINVAL
+    assert lib.drr_render(None, ctypes.byref(v), ctypes.byref(good), None, -1, None, None,
+                          None) == _lib.DRR_EINVAL
+    # n_poses == 0 is a valid no-op, even with NULL buffers
+    assert lib.drr_render(None, ctypes.byref(v), ctypes.byref(good), None, 0, None, None,
+                          None) == _lib.DRR_OK
+    # workspace queries
+    assert lib.drr_backward_workspace_bytes(ctypes.byref(good), 3) >= 3 * 7 * 8
+    assert lib.drr_ncc_workspace_bytes(2, 100) >= 2 * 5 * 8
+    assert lib.drr_backward_workspace_bytes(ctypes.byref(bad), 3) == 0
+
+
+def test_workspace_too_small_rejected():
+    lib = _lib.load()
+    det = _lib.detector_desc(16, 16, 1.0, 1.0)
+    st = lib.drr_render_backward(ctypes.byref(det), 2, ctypes.c_void_p(16), ctypes.c_void_p(16),
+                                 ctypes.c_void_p(16), ctypes.c_void_p(16), 8, None)
+    assert st == _lib.DRR_ENOMEM
+
+
+def test_plan_rejects_bad_descriptors():
+    lib = _lib.load()
+    desc = _lib.PlanDesc()
+    desc.max_items = 0
+    out = ctypes.c_void_p()
+    assert lib.drr_plan_create(ctypes.byref(desc), None, 0, None,
+                               ctypes.byref(out)) == _lib.DRR_EINVAL
+    assert lib.drr_plan_execute(None, None, 0, None) == _lib.DRR_EINVAL

@@ -1,0 +1,200 @@
+"""GPU pose gradients and the NCC loss against the FP64 oracle.
+
+Jacobians are compared with the oracle's frozen-index Jacobian (itself pinned
+to central differences), and with FP64 central differences of the oracle on
+pixels whose voxel sequence does not change within the step (kink-free).
+"""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import make_phantom, random_poses
+from tests._parity import assert_image_close, column_errors
+
+pytestmark = pytest.mark.gpu
+
+DEV = "cuda"
+# FP32 per-ray sums against the FP64 frozen-index Jacobian, relative to each
+# parameter's largest entry.
+JAC_RTOL = 2e-4
+# Central-difference check of the benchmark spec on kink-free pixels.
+FD_RTOL = 1e-3
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+
+
+@pytest.fixture(scope="module")
+def small():
+    import paper_2208_12737_amd as P
+    ph = make_phantom("small", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    return ph, vol, oracle.Grid(ph.volume, ph.spacing, ph.origin)
+
+
+def _gpu(a):
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).to(DEV)
+
+
+@pytest.mark.parametrize("seed", [0, 3])
+def test_jacobian_matches_oracle(small, seed):
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    poses = random_poses(2, math.pi / 8, 10.0, 1000.0, seed=seed)
+    det = P.Detector(48, 40, 2.5, 2.5)
+    img, jac = P.render(vol, _gpu(poses), det, jacobian=True)
+    rimg, rjac = oracle.render_jacobian(grid, poses.astype(np.float64), 48, 40, 2.5, 2.5,
+                                        nthreads=4)
+    assert_image_close(img.cpu().numpy(), rimg)
+    err = column_errors(jac.cpu().numpy(), rjac)
+    assert np.all(err <= JAC_RTOL), err
+
+
+def test_jacobian_vs_central_differences(small):
+    """Per-pixel d image / d pose against FP64 central differences of the
+    oracle with steps 1e-4 rad / 1e-3 mm, on kink-free pixels."""
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    pose = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=4)
+    det = P.Detector(32, 32, 4.0, 4.0)
+    _, jac = P.render(vol, _gpu(pose), det, jacobian=True)
+    jac = jac.cpu().numpy()[0]
+    steps = [1e-4] * 3 + [1e-3] * 3 + [1e-3]
+    fd, ok = oracle.render_fd(grid, pose[0].astype(np.float64), 32, 32, 4.0, 4.0, steps,
+                              nthreads=4)
+    for j in range(7):
+        m = ok[:, :, j]
+        assert m.mean() > 0.3
+        scale = np.abs(fd[:, :, j][m]).max()
+        err = np.abs(jac[:, :, j][m] - fd[:, :, j][m]).max() / scale
+        assert err <= FD_RTOL, (j, err)
+
+
+def test_backward_stored_and_retrace(small):
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    poses = random_poses(3, math.pi / 8, 10.0, 1000.0, seed=5)
+    det = P.Detector(40, 44, 2.0, 2.0)
+    rng = np.random.default_rng(1)
+    g = rng.normal(size=(3, 40, 44)).astype(np.float32)
+    _, jac = P.render(vol, _gpu(poses), det, jacobian=True)
+    gp = P.render_backward(det, jac, _gpu(g)).cpu().numpy()
+    gr = P.render_backward_retrace(vol, _gpu(poses), det, _gpu(g)).cpu().numpy()
+    _, rjac = oracle.render_jacobian(grid, poses.astype(np.float64), 40, 44, 2.0, 2.0,
+                                     nthreads=4)
+    ref = np.einsum("bhw,bhwj->bj", g.astype(np.float64), rjac)
+    scale = np.abs(rjac).max(axis=(1, 2)) * np.abs(g).sum(axis=(1, 2))[:, None]
+    assert np.all(np.abs(gp - ref) <= JAC_RTOL * scale)
+    assert np.all(np.abs(gr - ref) <= JAC_RTOL * scale)
+    np.testing.assert_allclose(gp, gr, rtol=1e-5, atol=1e-6 * np.abs(gp).max())
+
+
+def test_autograd_function(small):
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    poses = _gpu(random_poses(2, math.pi / 8, 10.0, 1000.0, seed=6))
+    det = P.Detector(32, 32, 4.0, 4.0)
+    g = torch.randn((2, 32, 32), device=DEV)
+    for retrace in (False, True):
+        p = poses.clone().requires_grad_(True)
+        img = P.drr(vol, p, det, retrace=retrace)
+        (img * g).sum().backward()
+        _, jac = P.render(vol, poses, det, jacobian=True)
+        ref = P.render_backward(det, jac, g)
+        torch.testing.assert_close(p.grad, ref, rtol=1e-5, atol=1e-5 * ref.abs().max().item())
+
+
+def test_ncc_forward_backward():
+    import paper_2208_12737_amd as P
+    rng = np.random.default_rng(2)
+    I = rng.uniform(0, 5, (3, 37, 29))
+    T = rng.uniform(0, 5, (3, 37, 29))
+    It, Tt = _gpu(I), _gpu(T).requires_grad_(False)
+    x = It.clone().requires_grad_(True)
+    loss = P.ncc_loss(x, Tt)
+    gl = torch.tensor([1.0, -2.0, 0.5], device=DEV)
+    (loss * gl).sum().backward()
+    for b in range(3):
+        z, gz = oracle.zncc_grad(It[b].cpu().numpy().astype(np.float64), T[b].astype(np.float32))
+        assert loss[b].item() == pytest.approx(-z, abs=1e-6)
+        np.testing.assert_allclose(x.grad[b].cpu().numpy(), -gl[b].item() * gz, rtol=1e-4,
+                                   atol=1e-5 * np.abs(gz).max())
+    # one target shared by all images
+    loss2 = P.ncc_loss(It, Tt[0])
+    for b in range(3):
+        z = oracle.zncc(It[b].cpu().numpy(), T[0].astype(np.float32))
+        assert loss2[b].item() == pytest.approx(-z, abs=1e-6)
+
+
+def test_fused_ncc_gradient_matches_oracle(small):
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    det = P.Detector(40, 40, 3.0, 3.0)
+    gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=8)
+    moving = random_poses(3, math.pi / 8, 10.0, 1000.0, seed=9)
+    target = P.render(vol, _gpu(gt), det)
+    loss, grad, img = P.render_ncc_grad(vol, _gpu(moving), det, target[0], return_image=True)
+    T = target.cpu().numpy()[0].astype(np.float64)
+    rimg, rjac = oracle.render_jacobian(grid, moving.astype(np.float64), 40, 40, 3.0, 3.0,
+                                        nthreads=4)
+    assert_image_close(img.cpu().numpy(), rimg)
+    for b in range(3):
+        z, gz = oracle.zncc_grad(rimg[b], T)
+        assert loss[b].item() == pytest.approx(-z, abs=2e-6)
+        ref = -np.einsum("hw,hwj->j", gz, rjac[b])
+        scale = np.abs(gz).sum() * np.abs(rjac[b]).max(axis=(0, 1))
+        assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (b, grad[b], ref)
+    # the fused path equals render -> ncc_loss -> autograd
+    p = _gpu(moving).requires_grad_(True)
+    l2 = P.ncc_loss(P.drr(vol, p, det), target[0])
+    l2.sum().backward()
+    torch.testing.assert_close(l2, loss, rtol=1e-5, atol=1e-6)
+    torch.testing.assert_close(p.grad, grad, rtol=1e-4, atol=1e-4 * grad.abs().max().item())
+
+
+def test_masked_ncc_gradient_vs_central_differences(small):
+    """d(-ZNCC)/d pose over the pixels that are kink-free for a parameter,
+    with the GPU Jacobian, against FP64 central differences of the oracle's
+    masked loss (BJ steps)."""
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    H = W = 32
+    det = P.Detector(H, W, 4.0, 4.0)
+    gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=12)[0].astype(np.float64)
+    pose = gt + np.array([0.03, -0.02, 0.04, 1.5, -1.0, 2.0, 0.0])
+    T, _, _ = oracle.render(grid, gt, H, W, 4.0, 4.0)
+    _, jac = P.render(vol, _gpu(pose[None]), det, jacobian=True)
+    jac = jac.cpu().numpy()[0].astype(np.float64)
+    steps = [1e-4] * 3 + [1e-3] * 3 + [1e-3]
+    I0, _, h0 = oracle.render(grid, pose, H, W, 4.0, 4.0)
+    for j in range(7):
+        pp, pm = pose.copy(), pose.copy()
+        pp[j] += steps[j]
+        pm[j] -= steps[j]
+        Ip, _, hp = oracle.render(grid, pp, H, W, 4.0, 4.0)
+        Im, _, hm = oracle.render(grid, pm, H, W, 4.0, 4.0)
+        m = ((hp == h0) & (hm == h0))[0]
+        fd = (-oracle.zncc(Ip[0][m], T[0][m]) + oracle.zncc(Im[0][m], T[0][m])) / (2 * steps[j])
+        _, gz = oracle.zncc_grad(I0[0][m], T[0][m])
+        an = -(gz * jac[:, :, j][m]).sum()
+        assert abs(an - fd) <= FD_RTOL * max(abs(fd), 1e-3 * np.abs(gz).sum() * np.abs(jac[:, :, j][m]).max()), (j, an, fd)
+
+
+def test_momentum_step():
+    import paper_2208_12737_amd as P
+    rng = np.random.default_rng(3)
+    p = rng.normal(size=(5, 7)).astype(np.float32)
+    v = rng.normal(size=(5, 7)).astype(np.float32)
+    g = rng.normal(size=(5, 7)).astype(np.float32)
+    r = rng.uniform(0, 1, (5, 7)).astype(np.float32)
+    pt, vt = _gpu(p), _gpu(v)
+    P.momentum_step(pt, vt, _gpu(g), _gpu(r), 0.9)
+    v2 = 0.9 * v + g
+    np.testing.assert_allclose(vt.cpu().numpy(), v2, rtol=1e-6)
+    np.testing.assert_allclose(pt.cpu().numpy(), p - r * v2, rtol=1e-5, atol=1e-6)
