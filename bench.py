@@ -5,12 +5,17 @@ phantom with a bone-like shell), 256 x 256 detector at 1.4 mm, SDD 1020 mm,
 256 random poses (angles +-pi/6, shifts +-30 mm) per batch.
 
 One step = one pass of the hot path over the batch:
-  forward     all 256 DRRs in one launch                 (timed: fwd)
+  forward     all 256 DRRs through a batched plan: one persistent tile-queue
+              launch replayed from a captured HIP graph, launch shape chosen
+              by the autotuner                                (timed: fwd)
   fwd + bwd   all 256 DRRs, negative ZNCC against per-pose targets and the
-              pose gradient, in one fused tracing launch  (timed: fwd+bwd)
-The printed JSON line reports forward DRRs/s as `value`, with fwd+bwd
-throughput, voxel-gather rates, latency percentiles, the HBM roofline of the
-forward kernel and the FP64 CPU oracle timed on a bounded sample.
+              pose gradient, in one fused tracing launch      (timed: fwd+bwd)
+  direct      the same 256 forward DRRs through the plain drr_render call
+              (one launch, no plan)                           (timed: direct)
+The printed JSON line reports forward DRRs/s of the plan as `value`, with
+fwd+bwd throughput, voxel-gather rates, latency percentiles, the HBM
+roofline of the forward kernel and the FP64 CPU oracle timed on a bounded
+sample.
 """
 
 from __future__ import annotations
@@ -40,7 +45,7 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=20.0,
                     help="approximate CPU time (thread-seconds) for the oracle sample")
-    ap.add_argument("--only", choices=["fwd", "fwdbwd"], default=None,
+    ap.add_argument("--only", choices=["fwd", "fwdbwd", "direct"], default=None,
                     help="time one phase only (for profiling runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (reference kernel "
@@ -58,6 +63,42 @@ def copy_calibration():
     torch.cuda.synchronize()
     print(json.dumps({"copy_calibration_bytes_read": 4 * n, "copy_calibration_bytes_written": 4 * n,
                       "launches": 3}), flush=True)
+
+
+def _source_digest():
+    """Digest of the kernel sources, to tell whether a stored profile still
+    describes the kernels that run."""
+    import hashlib
+    import glob
+    h = hashlib.sha256()
+    here = os.path.dirname(os.path.abspath(__file__))
+    for f in sorted(glob.glob(os.path.join(here, "paper_2208_12737_amd", "csrc", "*"))):
+        with open(f, "rb") as fh:
+            h.update(os.path.basename(f).encode())
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def profiled_traffic(plan_cfg):
+    """HBM-side bytes per forward launch from the committed rocprofv3 counter
+    summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy kernel), or None
+    when the kernel sources or launch shape changed since it was taken."""
+    here = os.path.dirname(os.path.abspath(__file__))
+    path = os.path.join(here, "profiles", "render_fwd_ct512_det256_poses256.md")
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    import re
+    m = re.search(r"```json\n(.*?)\n```", text, re.S)
+    if not m:
+        return None
+    rec = json.loads(m.group(1))
+    if rec.get("source_digest") != _source_digest():
+        return None
+    if rec.get("tile_code") != plan_cfg["tile_code"] or rec.get("wg_per_cu") != plan_cfg["wg_per_cu"]:
+        return None
+    return rec.get("traffic_bytes_per_launch")
 
 
 def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
@@ -132,7 +173,16 @@ def main():
     loss = torch.empty((nb,), dtype=torch.float32, device=dev)
     grad = torch.empty((nb, 7), dtype=torch.float32, device=dev)
 
+    from paper_2208_12737_amd.plan import Item, Plan
+    items = [Item(0, det, poses[b], img[b]) for b in range(nb)]
+    print("[bench] autotuning the batched plan", file=sys.stderr, flush=True)
+    plan = Plan([vol], max_items=nb, use_graph=True, autotune=True, tune_items=items)
+    plan_cfg = plan.config
+
     def fwd():
+        plan.execute(items)
+
+    def direct():
         L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc),
                ctypes.byref(det.desc), poses.data_ptr(), nb, img.data_ptr(), None,
                stream.cuda_stream)
@@ -142,7 +192,7 @@ def main():
                ctypes.byref(det.desc), moving.data_ptr(), nb, targets.data_ptr(), H * W, None,
                loss.data_ptr(), grad.data_ptr(), ws.data_ptr(), ws.numel(), stream.cuda_stream)
 
-    phases = [("fwd", fwd), ("fwdbwd", fwdbwd)]
+    phases = [("fwd", fwd), ("fwdbwd", fwdbwd), ("direct", direct)]
     if args.only:
         phases = [p for p in phases if p[0] == args.only]
 
@@ -178,7 +228,7 @@ def main():
     lat = []
     one = poses[:1].clone()
     img1 = torch.empty((1, H, W), dtype=torch.float32, device=dev)
-    for i in range(args.latency_reps + 10):
+    for i in range(args.latency_reps + 10 if args.latency_reps > 0 else 0):
         torch.cuda.synchronize()
         t = time.perf_counter()
         L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc),
@@ -204,9 +254,16 @@ def main():
         res["gathers_per_ray_fwd"] = gathers_fwd / pixels
         achieved = bytes_fwd / t_fwd / 1e9
         res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
-                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                           "kernel": "render_flat<8,2,2,kImage>",
+                           "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                           "traffic": profiled_traffic(plan_cfg),
+                           "kernel": f"render_persistent (image mode, tile code "
+                                     f"{plan_cfg['tile_code']}, {plan_cfg['wg_per_cu']} WG/CU)",
                            "bytes_per_launch": bytes_fwd}
+        res["plan"] = plan_cfg
+    if "direct" in times:
+        t_d = times["direct"].mean() / 1e3
+        res["direct_drrs_per_s"] = nb / t_d
+        res["direct_ms_per_batch"] = float(times["direct"].mean())
     if "fwdbwd" in times:
         t_fb = times["fwdbwd"].mean() / 1e3
         res["fwdbwd_drrs_per_s"] = nb / t_fb
@@ -216,9 +273,10 @@ def main():
             res["value"] = nb / t_fb
     res["p50_ms"] = float(np.percentile(step_ms, 50))
     res["p99_ms"] = float(np.percentile(step_ms, 99))
-    res["single_drr_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
-                                    "p99": float(np.percentile(lat, 99)),
-                                    "drrs_per_s": float(1e3 / lat.mean())}
+    if len(lat):
+        res["single_drr_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
+                                        "p99": float(np.percentile(lat, 99)),
+                                        "drrs_per_s": float(1e3 / lat.mean())}
     res["wall_s_timed"] = wall
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

@@ -202,6 +202,8 @@ typedef struct drr_plan_desc {
     int32_t use_graph;                   /* 1: capture the launch in a HIP graph */
     int32_t autotune;                    /* 1: time candidate launch shapes at create */
     const char* tune_cache_path;         /* NULL or a file for autotune results */
+    int32_t tile_code;                   /* without autotune: launch shape (-1 = default) */
+    int32_t wg_per_cu;                   /* without autotune: workgroups per CU (0 = max) */
 } drr_plan_desc;
 
 typedef struct drr_plan drr_plan;
@@ -225,6 +227,12 @@ int32_t drr_plan_config(const drr_plan* plan, int32_t* tile_code, int32_t* wg_pe
 void drr_plan_destroy(drr_plan* plan);
 
 /* ---------------------------------------------------------------- misc */
+
+/* Resident workgroups per CU for the direct render entry points (those not
+ * going through a plan); 0 = as many as registers allow.  The default (4)
+ * trades occupancy for cache locality of the voxel gathers.  Process-wide;
+ * affects launches enqueued after the call. */
+int32_t drr_set_launch_occupancy(int32_t wg_per_cu);
 
 const char* drr_status_string(int32_t status);
 const char* drr_last_error(void);

@@ -27,10 +27,32 @@ int32_t check_launch(const char* what)
     return DRR_OK;
 }
 
-// Default launch shape of the flat entry points: 8 x 8-pixel wave tiles,
-// 2 x 2 waves per workgroup (16 x 16 pixels, 256 threads).
-constexpr int kTW = 8, kWX = 2, kWY = 2;
+// Launch shape of the direct (non-plan) entry points: 8 x 8-pixel wave
+// tiles, 4 waves stacked along the detector rows (8 x 32 pixels, 256
+// threads).  Fewer resident workgroups per CU than the register file allows
+// keep the gather working set inside the L1/L2 caches; the limit is imposed
+// by reserving LDS per workgroup (default 4 workgroups = 4 waves per SIMD).
+constexpr int kTW = 8, kWX = 1, kWY = 4;
 using DefaultShape = TileShape<kTW, kWX, kWY>;
+
+static int g_wg_per_cu = 4;
+
+static size_t occupancy_lds(int wg_per_cu)
+{
+    static int lds_per_cu = -1;
+    if (lds_per_cu < 0) {
+        int dev = 0, v = 0;
+        hipGetDevice(&dev);
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+                hipSuccess || v <= 0)
+            v = 160 * 1024;
+        lds_per_cu = v;
+    }
+    if (wg_per_cu <= 0) return 0;
+    // a little below the share so that the static LDS of the kernel still fits
+    size_t share = (size_t)lds_per_cu / (size_t)wg_per_cu;
+    return share > 1024 ? share - 1024 : 0;
+}
 
 struct FlatGrid {
     int tiles_x, tiles_y, wg_per_pose;
@@ -55,7 +77,8 @@ static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
     const uint64_t blocks = (uint64_t)g.wg_per_pose * (uint64_t)n_poses;
     if (blocks > 0x7FFFFFFFull) return fail(DRR_ENOTSUP, "too many tiles in one launch");
     hipLaunchKernelGGL((render_flat<kTW, kWX, kWY, MODE>), dim3((unsigned)blocks),
-                       dim3(DefaultShape::threads), 0, stream, vol_args(packed, vol),
+                       dim3(DefaultShape::threads), occupancy_lds(g_wg_per_cu), stream,
+                       vol_args(packed, vol),
                        det_args(det), poses, g.tiles_x, g.wg_per_pose, image, jac, counts, aux,
                        aux_stride, partials);
     return check_launch("render kernel launch");
@@ -72,6 +95,14 @@ extern "C" {
 const char* drr_last_error(void) { return g_err; }
 
 int32_t drr_version(void) { return 10000; }
+
+int32_t drr_set_launch_occupancy(int32_t wg_per_cu)
+{
+    if (wg_per_cu < 0 || wg_per_cu > 64)
+        return fail(DRR_EINVAL, "set_launch_occupancy: %d outside [0, 64]", wg_per_cu);
+    g_wg_per_cu = wg_per_cu;
+    return DRR_OK;
+}
 
 const char* drr_status_string(int32_t s)
 {

@@ -135,6 +135,9 @@ static const ShapeInfo kShapes[] = {
     {16, 1, 4},   // 3: 16 x 16 px, 16 x 4 wave tiles
     {4, 4, 1},    // 4: 16 x 16 px,  4 x 16 wave tiles
     {8, 4, 1},    // 5: 32 x  8 px
+    {4, 1, 4},    // 6:  4 x 64 px,  4 x 16 wave tiles
+    {2, 2, 2},    // 7:  4 x 64 px,  2 x 32 wave tiles
+    {1, 4, 1},    // 8:  4 x 64 px,  1 x 64 wave tiles
 };
 constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
@@ -149,7 +152,10 @@ static PersistentFn persistent_fn(int code)
     case 2: return render_persistent<8, 1, 4, MODE>;
     case 3: return render_persistent<16, 1, 4, MODE>;
     case 4: return render_persistent<4, 4, 1, MODE>;
-    default: return render_persistent<8, 4, 1, MODE>;
+    case 5: return render_persistent<8, 4, 1, MODE>;
+    case 6: return render_persistent<4, 1, 4, MODE>;
+    case 7: return render_persistent<2, 2, 2, MODE>;
+    default: return render_persistent<1, 4, 1, MODE>;
     }
 }
 
@@ -417,7 +423,9 @@ static int32_t autotune(drr_plan* p, const drr_work_item* items, int n, hipStrea
     }
     float best = 1e30f;
     int best_code = 0, best_wpc = 0;
-    const int wpcs[] = {0, 2};   // occupancy limit, or two workgroups per CU
+    // resident workgroups per CU: the register limit, or fewer (less cache
+    // pressure from concurrent rays)
+    const int wpcs[] = {0, 3, 4, 5, 6};
     for (int c = 0; c < kNumShapes; ++c) {
         for (int w : wpcs) {
             p->tile_code = c;
@@ -493,6 +501,14 @@ int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_ite
             return fail(DRR_ENOMEM, "plan_create: allocation failed");
         }
         s.h_items = (PlanItem*)((char*)s.h_header + sizeof(PlanHeader));
+    }
+    if (!desc->autotune) {
+        if (desc->tile_code >= kNumShapes) {
+            free_plan(p);
+            return fail(DRR_EINVAL, "plan_create: tile_code must be < %d", kNumShapes);
+        }
+        p->tile_code = desc->tile_code >= 0 ? desc->tile_code : 0;
+        p->wg_per_cu = desc->wg_per_cu > 0 ? desc->wg_per_cu : 0;
     }
     int32_t rc = compute_grids(p);
     if (rc == DRR_OK && desc->autotune) {

@@ -190,30 +190,38 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     const int32_t pitch_y = V.n[2] + 2;
     const int32_t pitch_x = (V.n[1] + 2) * pitch_y;
     const int32_t pitch[3] = {pitch_x * 4, pitch_y * 4, 4};   // bytes
-    double an[3], da[3];
-    int32_t stride[3];
-    uint32_t off = 0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) {
-        double f = floor((s[c] + ae * d[c] - o[c]) / sp[c]);
-        int32_t i = (int32_t)fmin(fmax(f, 0.0), (double)(V.n[c] - 1));
-        off += (uint32_t)((i + 1) * pitch[c]);
+    // Per-axis state as named scalars (no arrays: a select between array
+    // elements in the loop would be lowered to an indexed memory load).
+    struct Axis {
+        double a, da;
+        uint32_t stride;
+        uint32_t off;
+    };
+    auto axis = [&](int c) {
+        Axis x;
+        const double f = floor((s[c] + ae * d[c] - o[c]) / sp[c]);
+        const int32_t i = (int32_t)fmin(fmax(f, 0.0), (double)(V.n[c] - 1));
+        x.off = (uint32_t)((i + 1) * pitch[c]);
         if (d[c] > 0.0) {
-            an[c] = (o[c] + (double)(i + 1) * sp[c] - s[c]) / d[c];
-            da[c] = sp[c] / d[c];
-            stride[c] = pitch[c];
+            x.a = (o[c] + (double)(i + 1) * sp[c] - s[c]) / d[c];
+            x.da = sp[c] / d[c];
+            x.stride = (uint32_t)pitch[c];
         } else if (d[c] < 0.0) {
-            an[c] = (o[c] + (double)i * sp[c] - s[c]) / d[c];
-            da[c] = -sp[c] / d[c];
-            stride[c] = -pitch[c];
+            x.a = (o[c] + (double)i * sp[c] - s[c]) / d[c];
+            x.da = -sp[c] / d[c];
+            x.stride = (uint32_t)(-pitch[c]);
         } else {
-            an[c] = __builtin_inf();
-            da[c] = 0.0;
-            stride[c] = 0;
+            x.a = __builtin_inf();
+            x.da = 0.0;
+            x.stride = 0u;
         }
-    }
-
-    double ax = an[0], ay = an[1], az = an[2];
+        return x;
+    };
+    const Axis X0 = axis(0), Y0 = axis(1), Z0 = axis(2);
+    double ax = X0.a, ay = Y0.a, az = Z0.a;
+    const double dax = X0.da, day = Y0.da, daz = Z0.da;
+    const uint32_t sx = X0.stride, sy = Y0.stride, sz = Z0.stride;
+    uint32_t off = X0.off + Y0.off + Z0.off;
     double acc = 0.0;
     int32_t nseg = 0;
     float vprev = 0.0f;
@@ -221,39 +229,48 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     float A0 = 0.f, A1 = 0.f, B0 = 0.f, B1 = 0.f, An = 0.f, Bn = 0.f;
 
     // One merge step: close the segment [a_start, next crossing] in the
-    // current voxel (value vc), advance the winning axes and issue the load
+    // current voxel (value vc), advance the winning axis and issue the load
     // of the next voxel into vn.  The loop below alternates the roles of
     // (v0, a0) and (v1, a1) so that no register copy forces an early wait on
     // the load: its latency overlaps the next step's merge arithmetic.
-    auto step = [&](const float vc, float& vn, const double a_start, double& a_end) {
-        const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));
-        const bool bx = ax == anext, by = ay == anext, bz = az == anext;
-        ax = bx ? ax + da[0] : ax;
-        ay = by ? ay + da[1] : ay;
-        az = bz ? az + da[2] : az;
-        off += (bx ? (uint32_t)stride[0] : 0u) + (by ? (uint32_t)stride[1] : 0u) +
-               (bz ? (uint32_t)stride[2] : 0u);
-        vn = ld(rsrc, off);
-        const double seg = anext - a_start;
-        acc = fma(seg, (double)vc, acc);
-        if (COUNT) nseg += seg > kSliver ? 1 : 0;
-        if (JAC) {
-            // crossing at a_start: V_before = vprev, V_after = vc.  A step
-            // taken after the ray has ended (a_start == amax) is empty.
-            const bool live = a_start < amax;
-            const float dl = live ? vprev - vc : 0.0f;
-            const float t = (float)(a_start - amin);
-            A0 += idprev == 0 ? dl : 0.0f;
-            B0 += idprev == 0 ? t * dl : 0.0f;
-            A1 += idprev == 1 ? dl : 0.0f;
-            B1 += idprev == 1 ? t * dl : 0.0f;
-            An += idprev < 0 ? dl : 0.0f;
-            Bn += idprev < 0 ? t * dl : 0.0f;
-            vprev = live ? vc : vprev;
-            idprev = bx ? 0 : (by ? 1 : 2);
-        }
-        a_end = anext;
-    };
+    // (A macro rather than a lambda: a by-reference closure makes the
+    // compiler keep the strides on the stack and load them every step.)
+    //
+    // Exactly one axis advances per step (x before y before z).  Tied
+    // crossings are therefore taken one per step, the later ones closing
+    // zero-length segments; the voxel sequence and the sum are unchanged.
+    // When anext is the exit, z "advances" harmlessly: the ray is done.
+#define DRR_MERGE_STEP(vc, vn, a_start, a_end)                                   \
+    do {                                                                         \
+        const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));           \
+        const bool bx = ax == anext;                                             \
+        const bool by = !bx && ay == anext;                                      \
+        const bool bz = !bx && !by;                                              \
+        ax = fma(bx ? 1.0 : 0.0, dax, ax);                                       \
+        ay = fma(by ? 1.0 : 0.0, day, ay);                                       \
+        az = fma(bz ? 1.0 : 0.0, daz, az);                                       \
+        off += bx ? sx : (by ? sy : sz);                                         \
+        vn = ld(rsrc, off);                                                      \
+        const double seg = anext - (a_start);                                    \
+        acc = fma(seg, (double)(vc), acc);                                       \
+        if (COUNT) nseg += seg > kSliver ? 1 : 0;                                \
+        if (JAC) {                                                               \
+            /* crossing at a_start: V_before = vprev, V_after = vc; a step    */ \
+            /* taken after the ray has ended (a_start == amax) is empty       */ \
+            const bool live = (a_start) < amax;                                  \
+            const float dl = live ? vprev - (vc) : 0.0f;                         \
+            const float t = (float)((a_start) - amin);                           \
+            A0 += idprev == 0 ? dl : 0.0f;                                       \
+            B0 += idprev == 0 ? t * dl : 0.0f;                                   \
+            A1 += idprev == 1 ? dl : 0.0f;                                       \
+            B1 += idprev == 1 ? t * dl : 0.0f;                                   \
+            An += idprev < 0 ? dl : 0.0f;                                        \
+            Bn += idprev < 0 ? t * dl : 0.0f;                                    \
+            vprev = live ? (vc) : vprev;                                         \
+            idprev = bx ? 0 : (by ? 1 : 2);                                      \
+        }                                                                        \
+        a_end = anext;                                                           \
+    } while (0)
 
     float v0 = ld(rsrc, off), v1 = 0.0f;
     double a0 = amin, a1 = amin;
@@ -268,12 +285,13 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // unconditional keeps the first step's load ahead of its use.
     for (int it = 0; it < cap; ++it) {
         if (active) {
-            step(v0, v1, a0, a1);
-            step(v1, v0, a1, a0);
+            DRR_MERGE_STEP(v0, v1, a0, a1);
+            DRR_MERGE_STEP(v1, v0, a1, a0);
             active = a0 < amax;
         }
         if (__builtin_amdgcn_ballot_w64(active) == 0) break;
     }
+#undef DRR_MERGE_STEP
     if (JAC) {
         // exit crossing at amax: V_before = last voxel, V_after = 0
         const float t = (float)(amax - amin);

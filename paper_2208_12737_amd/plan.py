@@ -60,7 +60,7 @@ class Plan:
 
     def __init__(self, volumes: Sequence[Volume], max_items: int = 1024, use_graph: bool = True,
                  autotune: bool = False, tune_items: Optional[Sequence[Item]] = None,
-                 cache_path: Optional[str] = None):
+                 cache_path: Optional[str] = None, tile_code: int = -1, wg_per_cu: int = 0):
         self.volumes = list(volumes)
         self._descs = (_lib.VolumeDesc * len(self.volumes))(*[v.desc for v in self.volumes])
         self._packed = (ctypes.c_void_p * len(self.volumes))(
@@ -74,6 +74,8 @@ class Plan:
         d.autotune = 1 if autotune else 0
         self._cache = cache_path.encode() if cache_path else None
         d.tune_cache_path = self._cache
+        d.tile_code = tile_code
+        d.wg_per_cu = wg_per_cu
         self._desc = d
         tune = list(tune_items or [])
         arr = _items_array(tune) if tune else None
