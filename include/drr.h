@@ -60,10 +60,24 @@ extern "C" {
 #define DRR_EHIP (-3)     /* HIP runtime error (launch, copy, graph) */
 #define DRR_ENOTSUP (-4)  /* unsupported size (e.g. volume beyond 2^30 packed voxels) */
 
+/* Memory layouts of the packed volume.  Both hold the voxels surrounded by a
+ * one-voxel border of zeros and give bitwise identical renders; they differ
+ * in speed only.
+ *   DRR_LAYOUT_INPUT     one copy in the caller's order (z fastest).
+ *   DRR_LAYOUT_PER_AXIS  three copies, one per principal ray axis: a pose
+ *                        whose central ray runs mostly along axis c reads the
+ *                        copy whose fastest-varying memory axis is the
+ *                        finer-spaced of the two other axes, so that the
+ *                        rays of neighbouring detector pixels gather from
+ *                        shared cache lines.  Three times the memory. */
+#define DRR_LAYOUT_INPUT 0
+#define DRR_LAYOUT_PER_AXIS 1
+
 typedef struct drr_volume_desc {
     int32_t nx, ny, nz;   /* voxels per axis, each >= 1 */
     double spacing[3];    /* voxel size per axis, mm, > 0 */
     double origin[3];     /* position of plane 0 per axis, mm (centred grid: -n*spacing/2) */
+    int32_t layout;       /* DRR_LAYOUT_* of the packed copy */
 } drr_volume_desc;
 
 typedef struct drr_detector_desc {
@@ -74,9 +88,8 @@ typedef struct drr_detector_desc {
 
 /* ---------------------------------------------------------------- volume */
 
-/* Bytes of the packed, render-ready copy of a volume (internal layout: the
- * voxels surrounded by a one-voxel border of zeros).  Returns 0 for an
- * invalid or unsupported descriptor. */
+/* Bytes of the packed, render-ready copy of a volume in the descriptor's
+ * layout.  Returns 0 for an invalid or unsupported descriptor. */
 size_t drr_volume_packed_bytes(const drr_volume_desc* vol);
 
 /* Packs the caller's C-order float32 volume `src` (device, nx*ny*nz floats)
@@ -229,7 +242,8 @@ void drr_plan_destroy(drr_plan* plan);
 /* ---------------------------------------------------------------- misc */
 
 /* Resident workgroups per CU for the direct render entry points (those not
- * going through a plan); 0 = as many as registers allow.  The default (4)
+ * going through a plan); 0 = as many as registers allow; -1 (default) = by
+ * volume layout (4 for DRR_LAYOUT_INPUT, 6 for DRR_LAYOUT_PER_AXIS), which
  * trades occupancy for cache locality of the voxel gathers.  Process-wide;
  * affects launches enqueued after the call. */
 int32_t drr_set_launch_occupancy(int32_t wg_per_cu);

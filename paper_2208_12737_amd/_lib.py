@@ -31,7 +31,8 @@ class DrrError(RuntimeError):
 
 class VolumeDesc(ctypes.Structure):
     _fields_ = [("nx", ctypes.c_int32), ("ny", ctypes.c_int32), ("nz", ctypes.c_int32),
-                ("spacing", ctypes.c_double * 3), ("origin", ctypes.c_double * 3)]
+                ("spacing", ctypes.c_double * 3), ("origin", ctypes.c_double * 3),
+                ("layout", ctypes.c_int32)]
 
 
 class DetectorDesc(ctypes.Structure):
@@ -121,8 +122,13 @@ def call(func: str, *args):
     return st
 
 
-def volume_desc(shape, spacing, origin) -> VolumeDesc:
+DRR_LAYOUT_INPUT = 0
+DRR_LAYOUT_PER_AXIS = 1
+
+
+def volume_desc(shape, spacing, origin, layout=DRR_LAYOUT_INPUT) -> VolumeDesc:
     d = VolumeDesc()
+    d.layout = int(layout)
     d.nx, d.ny, d.nz = (int(v) for v in shape)
     for c in range(3):
         d.spacing[c] = float(spacing[c])

@@ -22,9 +22,52 @@ inline bool finite_pos(double x) { return isfinite(x) && x > 0.0; }
 // Largest packed volume the 32-bit buffer offsets can address.
 constexpr uint64_t kMaxPackedBytes = 0xFFFFFF00ull;
 
-inline uint64_t packed_elems(const drr_volume_desc& v)
+// Elements of one zero-bordered copy of the grid.
+inline uint64_t copy_elems(const drr_volume_desc& v)
 {
     return (uint64_t)(v.nx + 2) * (uint64_t)(v.ny + 2) * (uint64_t)(v.nz + 2);
+}
+
+inline int num_copies(const drr_volume_desc& v)
+{
+    return v.layout == DRR_LAYOUT_PER_AXIS ? 3 : 1;
+}
+
+inline uint64_t packed_elems(const drr_volume_desc& v) { return copy_elems(v) * num_copies(v); }
+
+// Memory order of copy q (slowest axis first).  DRR_LAYOUT_INPUT keeps the
+// caller's (x, y, z).  DRR_LAYOUT_PER_AXIS: copy q serves rays running
+// mostly along axis q; q is the slowest axis and, of the other two, the one
+// with the finer spacing varies fastest.
+struct CopyOrder {
+    int axis[3];
+};
+
+inline CopyOrder copy_order(const drr_volume_desc& v, int q)
+{
+    CopyOrder o;
+    if (v.layout != DRR_LAYOUT_PER_AXIS) {
+        o.axis[0] = 0;
+        o.axis[1] = 1;
+        o.axis[2] = 2;
+        return o;
+    }
+    const int a = (q + 1) % 3, b = (q + 2) % 3;
+    const bool a_finer = v.spacing[a] < v.spacing[b] || (v.spacing[a] == v.spacing[b] && a > b);
+    o.axis[0] = q;
+    o.axis[1] = a_finer ? b : a;
+    o.axis[2] = a_finer ? a : b;
+    return o;
+}
+
+// Element pitch of each logical axis in copy q.
+inline void copy_pitch(const drr_volume_desc& v, int q, int64_t pitch[3])
+{
+    const int64_t P[3] = {v.nx + 2, v.ny + 2, v.nz + 2};
+    const CopyOrder o = copy_order(v, q);
+    pitch[o.axis[2]] = 1;
+    pitch[o.axis[1]] = P[o.axis[2]];
+    pitch[o.axis[0]] = P[o.axis[2]] * P[o.axis[1]];
 }
 
 inline int32_t validate_volume(const drr_volume_desc* v)
@@ -38,9 +81,11 @@ inline int32_t validate_volume(const drr_volume_desc* v)
             return fail(DRR_EINVAL, "volume spacing[%d] must be finite and > 0", c);
         if (!isfinite(v->origin[c])) return fail(DRR_EINVAL, "volume origin[%d] is not finite", c);
     }
-    if (packed_elems(*v) * 4ull > kMaxPackedBytes)
-        return fail(DRR_ENOTSUP, "packed volume of %llu bytes exceeds the 4 GiB buffer limit",
-                    (unsigned long long)(packed_elems(*v) * 4ull));
+    if (v->layout != DRR_LAYOUT_INPUT && v->layout != DRR_LAYOUT_PER_AXIS)
+        return fail(DRR_EINVAL, "unknown volume layout %d", v->layout);
+    if (copy_elems(*v) * 4ull > kMaxPackedBytes)
+        return fail(DRR_ENOTSUP, "packed volume copy of %llu bytes exceeds the 4 GiB buffer limit",
+                    (unsigned long long)(copy_elems(*v) * 4ull));
     return DRR_OK;
 }
 
@@ -67,7 +112,14 @@ inline VolArgs vol_args(const void* packed, const drr_volume_desc& v)
         a.spacing[c] = v.spacing[c];
         a.origin[c] = v.origin[c];
     }
-    a.bytes = (uint32_t)(packed_elems(v) * 4ull);
+    a.copy_bytes = (uint32_t)(copy_elems(v) * 4ull);
+    const int nc = num_copies(v);
+    for (int q = 0; q < 3; ++q) {
+        int64_t p[3];
+        copy_pitch(v, q < nc ? q : 0, p);
+        for (int c = 0; c < 3; ++c) a.pitch[q][c] = (int32_t)(p[c] * 4);
+        a.copy_for[q] = q < nc ? q : 0;
+    }
     return a;
 }
 

@@ -82,7 +82,7 @@ __device__ inline int next_tile(int32_t* counters, int total, int xcd, int* scan
 }
 
 template <int TW, int WX, int WY, int MODE>
-__global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* block,
+__global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __restrict__ block,
                                                                   int32_t* counters, int group)
 {
     using S = TileShape<TW, WX, WY>;
@@ -97,7 +97,9 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* bl
     for (;;) {
         if (threadIdx.x == 0) s_tile = next_tile(ctr, total, xcd, &scan);
         __syncthreads();
-        const int t = s_tile;
+        // uniform across the workgroup: keep the item lookup and the item's
+        // fields in scalar registers
+        const int t = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
         if (t < 0) break;
         // binary search: last item with tile_begin <= t
@@ -110,14 +112,13 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* bl
         const PlanItem& it = items[first + lo];
         const int local = t - it.tile_begin;
         const int ty = local / it.tiles_x, tx = local % it.tiles_x;
-        const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(it.vol);
         TileOut o;
         o.image = it.image;
         o.jac = it.jac;
         o.counts = it.counts;
         o.aux = nullptr;
         o.partial = nullptr;
-        render_tile<TW, WX, WY, MODE>(it.vol, rsrc, it.det, it.pose, tx, ty, o, lds);
+        render_tile<TW, WX, WY, MODE>(it.vol, it.det, it.pose, tx, ty, o, lds);
     }
     (void)sizeof(S);
 }
@@ -270,7 +271,7 @@ static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
 
 static void drop_graphs(Slot& s)
 {
-    for (auto& kv : s.graphs) hipGraphExecDestroy(kv.second);
+    for (auto& kv : s.graphs) (void)hipGraphExecDestroy(kv.second);
     s.graphs.clear();
 }
 
@@ -300,7 +301,7 @@ static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hi
             if (rc) return rc;
             if (e2 != hipSuccess) return fail(DRR_EHIP, "end capture: %s", hipGetErrorString(e2));
             e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
-            hipGraphDestroy(g);
+            (void)hipGraphDestroy(g);
             if (e != hipSuccess) return fail(DRR_EHIP, "graph instantiate: %s", hipGetErrorString(e));
             found = s.graphs.emplace(mask, ge).first;
         }
@@ -393,18 +394,18 @@ static int32_t time_config(drr_plan* p, const drr_work_item* items, int n, hipSt
     int32_t rc = compute_grids(p);
     if (rc) return rc;
     hipEvent_t a, b;
-    hipEventCreate(&a);
-    hipEventCreate(&b);
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess)
+        return fail(DRR_EHIP, "autotune: event creation failed");
     rc = execute_locked(p, items, n, st);   // warm-up (also captures the graph)
     const int reps = 3;
-    hipEventRecord(a, st);
+    (void)hipEventRecord(a, st);
     for (int r = 0; r < reps && rc == DRR_OK; ++r) rc = execute_locked(p, items, n, st);
-    hipEventRecord(b, st);
+    (void)hipEventRecord(b, st);
     hipError_t e = hipEventSynchronize(b);
     float t = 0.0f;
-    hipEventElapsedTime(&t, a, b);
-    hipEventDestroy(a);
-    hipEventDestroy(b);
+    (void)hipEventElapsedTime(&t, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
     if (rc) return rc;
     if (e != hipSuccess) return fail(DRR_EHIP, "autotune sync: %s", hipGetErrorString(e));
     *ms = t / reps;
@@ -451,12 +452,12 @@ static int32_t autotune(drr_plan* p, const drr_work_item* items, int n, hipStrea
 static void free_plan(drr_plan* p)
 {
     for (Slot& s : p->slots) {
-        if (s.used && s.done) hipEventSynchronize(s.done);
+        if (s.used && s.done) (void)hipEventSynchronize(s.done);
         drop_graphs(s);
-        if (s.done) hipEventDestroy(s.done);
-        if (s.h_header) hipHostFree(s.h_header);
-        if (s.d_block) hipFree(s.d_block);
-        if (s.d_counters) hipFree(s.d_counters);
+        if (s.done) (void)hipEventDestroy(s.done);
+        if (s.h_header) (void)hipHostFree(s.h_header);
+        if (s.d_block) (void)hipFree(s.d_block);
+        if (s.d_counters) (void)hipFree(s.d_counters);
     }
     delete p;
 }
@@ -487,8 +488,9 @@ int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_ite
         p->packed.push_back(desc->packed[v]);
     }
     int dev = 0;
-    hipGetDevice(&dev);
-    hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&p->num_cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess)
+        p->num_cus = 0;
     if (p->num_cus < 1) p->num_cus = 1;
     const size_t tb = table_bytes(p->max_items);
     for (Slot& s : p->slots) {

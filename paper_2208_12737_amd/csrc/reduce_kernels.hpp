@@ -169,16 +169,19 @@ __global__ void k_momentum(float* __restrict__ poses, float* __restrict__ vel,
     poses[i] = poses[i] - rate[i] * v;
 }
 
-// Copies a C-order volume into the zero-bordered packed layout.
+// Copies a C-order volume into one zero-bordered copy whose memory order is
+// (o0 slowest, o1, o2 fastest) over the padded dims P.
 __global__ void k_pack(const float* __restrict__ src, float* __restrict__ dst, int nx, int ny,
-                       int nz, uint64_t total)
+                       int nz, int o0, int o1, int o2, uint64_t total)
 {
     const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (e >= total) return;
-    const uint64_t pz = (uint64_t)nz + 2, py = (uint64_t)ny + 2;
-    const int k = (int)(e % pz);
-    const int j = (int)((e / pz) % py);
-    const int i = (int)(e / (pz * py));
+    const uint64_t P[3] = {(uint64_t)nx + 2, (uint64_t)ny + 2, (uint64_t)nz + 2};
+    uint64_t idx[3];
+    idx[o2] = e % P[o2];
+    idx[o1] = (e / P[o2]) % P[o1];
+    idx[o0] = e / (P[o2] * P[o1]);
+    const int i = (int)idx[0], j = (int)idx[1], k = (int)idx[2];
     float v = 0.0f;
     if (i >= 1 && i <= nx && j >= 1 && j <= ny && k >= 1 && k <= nz)
         v = src[((uint64_t)(i - 1) * ny + (j - 1)) * nz + (k - 1)];

@@ -67,9 +67,9 @@ __device__ inline void block_sums(double (&vals)[NS], double* lds, double* out)
 }
 
 template <int TW, int WX, int WY, int MODE>
-__device__ inline void render_tile(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
-                                   const DetArgs& D, const float* __restrict__ pose, int tx,
-                                   int ty, const TileOut& o, double* lds)
+__device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
+                                   const float* __restrict__ pose, int tx, int ty,
+                                   const TileOut& o, double* lds)
 {
     using S = TileShape<TW, WX, WY>;
     using T = ModeTraits<MODE>;
@@ -86,13 +86,31 @@ __device__ inline void render_tile(const VolArgs& V, const __amdgpu_buffer_rsrc_
     double s[3], d[3];
     ray_of(q, R, u, v, s, d);
 
+    // Copy of the volume for this pose: by the principal axis of its
+    // central ray (the direction of -R e_x), the same for the whole tile.
+    int principal = 0;
+    {
+        const double c0 = fabs(R.m[0][0]), c1 = fabs(R.m[1][0]), c2 = fabs(R.m[2][0]);
+        principal = (c1 > c0 && c1 >= c2) ? 1 : ((c2 > c0 && c2 > c1) ? 2 : 0);
+    }
+    // (selects, not indexing: a dynamic index into the argument block would
+    // be lowered to a scratch copy of it)
+    const int copy = __builtin_amdgcn_readfirstlane(
+        principal == 0 ? V.copy_for[0] : (principal == 1 ? V.copy_for[1] : V.copy_for[2]));
+    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(V, copy);
+    int32_t pitch[3];
+#pragma unroll
+    for (int c = 0; c < 3; ++c)
+        pitch[c] = __builtin_amdgcn_readfirstlane(
+            copy == 0 ? V.pitch[0][c] : (copy == 1 ? V.pitch[1][c] : V.pitch[2][c]));
+
     RayAcc r;
     r.sum = 0.0;
     r.amin = 0.0;
     r.a0 = r.a1 = r.b0 = r.b1 = r.a_none = r.b_none = 0.0f;
     r.nseg = 0;
     r.valid = true;
-    if (inside) r = trace<T::jac, T::count>(V, rsrc, s, d);
+    if (inside) r = trace<T::jac, T::count>(V, rsrc, pitch, s, d);
 
     const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const float E = r.valid ? (float)(L * r.sum) : __builtin_nanf("");
@@ -158,14 +176,13 @@ __global__ __launch_bounds__(64 * WX * WY) void render_flat(
     const int t = (int)(logical % (uint32_t)wg_per_pose);
     const int ty = t / tiles_x, tx = t % tiles_x;
     const int64_t hw = (int64_t)D.H * D.W;
-    const __amdgpu_buffer_rsrc_t rsrc = make_rsrc(V);
     TileOut o;
     o.image = image ? image + b * hw : nullptr;
     o.jac = jac ? jac + b * hw * 7 : nullptr;
     o.counts = counts ? counts + b * hw : nullptr;
     o.aux = aux ? aux + b * aux_stride : nullptr;
     o.partial = T::nsum > 0 ? partials + ((int64_t)b * wg_per_pose + t) * T::nsum : nullptr;
-    render_tile<TW, WX, WY, MODE>(V, rsrc, D, poses + 7 * b, tx, ty, o, lds);
+    render_tile<TW, WX, WY, MODE>(V, D, poses + 7 * b, tx, ty, o, lds);
 }
 
 }  // namespace drr

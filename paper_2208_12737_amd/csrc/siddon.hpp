@@ -30,12 +30,18 @@ constexpr uint32_t kBufferDword3 = 0x00020000u;  // gfx9 raw buffer, 32-bit data
 // always includes every segment.
 constexpr double kSliver = 0x1p-36;
 
+// A packed volume: one or three copies of the zero-bordered grid, each in
+// its own memory order.  pitch[q][c] is the byte distance between
+// neighbouring voxels along axis c in copy q; copy_for[c] names the copy read
+// by poses whose central ray runs mostly along axis c.
 struct VolArgs {
     const float* packed;
     double spacing[3];
     double origin[3];
     int32_t n[3];
-    uint32_t bytes;  // size of the packed buffer
+    uint32_t copy_bytes;
+    int32_t pitch[3][3];
+    int32_t copy_for[3];
 };
 
 struct DetArgs {
@@ -139,7 +145,7 @@ __device__ inline double min_nn(double a, double b)
 
 template <bool JAC, bool COUNT>
 __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
-                               const double s[3], const double d[3])
+                               const int32_t pitch[3], const double s[3], const double d[3])
 {
     RayAcc r;
     r.sum = 0.0;
@@ -187,9 +193,6 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
 
     // Voxel just past the entry, and each axis's first crossing after it.
     const double ae = amin + (amax - amin) * 0x1p-30;
-    const int32_t pitch_y = V.n[2] + 2;
-    const int32_t pitch_x = (V.n[1] + 2) * pitch_y;
-    const int32_t pitch[3] = {pitch_x * 4, pitch_y * 4, 4};   // bytes
     // Per-axis state as named scalars (no arrays: a select between array
     // elements in the loop would be lowered to an indexed memory load).
     struct Axis {
@@ -370,9 +373,10 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, const Ma
     J[6] = (float)js;
 }
 
-__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const VolArgs& V)
+__device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const VolArgs& V, int copy)
 {
-    return __builtin_amdgcn_make_buffer_rsrc((void*)V.packed, (short)0, (int)V.bytes,
+    const char* base = (const char*)V.packed + (size_t)copy * V.copy_bytes;
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)V.copy_bytes,
                                              (int)kBufferDword3);
 }
 

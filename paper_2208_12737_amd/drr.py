@@ -54,15 +54,21 @@ class Detector:
         return self.height * self.width
 
 
+LAYOUTS = {"input": _lib.DRR_LAYOUT_INPUT, "per_axis": _lib.DRR_LAYOUT_PER_AXIS}
+
+
 class Volume:
     """A CT volume packed into the renderer's layout and kept in HBM.
 
     data: float32 tensor of shape (nx, ny, nz) (C-order, any device);
     spacing: voxel size in mm; origin: position of plane 0 per axis (default
-    centres the grid on the world origin).
+    centres the grid on the world origin); layout: "per_axis" (three copies,
+    one per principal ray axis, fastest) or "input" (one copy).  Renders are
+    bitwise identical for both layouts.
     """
 
-    def __init__(self, data: torch.Tensor, spacing, origin=None, device=None):
+    def __init__(self, data: torch.Tensor, spacing, origin=None, device=None,
+                 layout: str = "per_axis"):
         if data.ndim != 3:
             raise ValueError("volume data must be 3-D (nx, ny, nz)")
         device = torch.device(device) if device is not None else (
@@ -73,7 +79,10 @@ class Volume:
         if origin is None:
             origin = tuple(-0.5 * n * s for n, s in zip(self.shape, self.spacing))
         self.origin = tuple(float(v) for v in origin)
-        self.desc = _lib.volume_desc(self.shape, self.spacing, self.origin)
+        if layout not in LAYOUTS:
+            raise ValueError(f"layout must be one of {sorted(LAYOUTS)}")
+        self.layout = layout
+        self.desc = _lib.volume_desc(self.shape, self.spacing, self.origin, LAYOUTS[layout])
         nbytes = _lib.load().drr_volume_packed_bytes(ctypes.byref(self.desc))
         if nbytes == 0:
             _lib.check("drr_volume_packed_bytes", _lib.DRR_EINVAL)

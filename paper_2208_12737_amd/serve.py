@@ -1,0 +1,294 @@
+"""Continuous-batching request loop over CT volumes resident in HBM.
+
+Requests (a volume, a detector, a pose, forward or forward + backward)
+arrive at any time.  Each scheduler tick
+  1. completes the batches whose device work has finished (non-blocking
+     event queries), releasing their memory and slots,
+  2. admits queued requests in arrival order while the in-flight memory
+     stays within the HBM budget and a slot is free (a request larger than
+     the whole budget is rejected at submission),
+  3. launches the admitted requests as one batch on the next of a few
+     streams: all forward requests in one persistent plan launch (any mix of
+     volumes and detector sizes), forward + backward requests as one fused
+     render + NCC + pose-gradient launch per (volume, detector) group.
+Batches on different streams overlap on the device, so requests that arrive
+while others run are admitted as soon as memory and slots free up.  Every
+result is computed by the same per-ray and per-pose kernels as a request
+served alone, with fixed-order reductions, so it is bitwise independent of
+the mix it was batched with.
+
+The scheduling logic is independent of the GPU: ``Server`` drives a backend
+object (``GpuBackend`` here, or a stand-in in tests).
+"""
+
+from __future__ import annotations
+
+import collections
+import ctypes
+import threading
+import time
+from dataclasses import dataclass, field
+from typing import Any, Callable, Dict, List, Optional
+
+import numpy as np
+
+FWD = "fwd"
+FWDBWD = "fwdbwd"
+
+
+class RequestRejected(RuntimeError):
+    pass
+
+
+@dataclass
+class Request:
+    volume: str
+    height: int
+    width: int
+    delta_x: float
+    delta_y: float
+    pose: np.ndarray                  # 7 floats (host)
+    kind: str = FWD                   # FWD or FWDBWD
+    target: Any = None                # device image [H, W] for FWDBWD
+    arrival: float = field(default_factory=time.perf_counter)
+
+
+class Ticket:
+    """Handle of a submitted request."""
+
+    def __init__(self, req: Request, nbytes: int):
+        self.request = req
+        self.nbytes = nbytes
+        self.done_at: Optional[float] = None
+        self.result: Any = None
+        self.error: Optional[BaseException] = None
+        self._event = threading.Event()
+
+    def done(self) -> bool:
+        return self._event.is_set()
+
+    def wait(self, timeout: Optional[float] = None):
+        if not self._event.wait(timeout):
+            raise TimeoutError("request not finished")
+        if self.error is not None:
+            raise self.error
+        return self.result
+
+    @property
+    def latency(self) -> Optional[float]:
+        return None if self.done_at is None else self.done_at - self.request.arrival
+
+    def _finish(self, result=None, error=None):
+        self.result, self.error = result, error
+        self.done_at = time.perf_counter()
+        self._event.set()
+
+
+class Server:
+    """Scheduler: admission by memory budget and slots, continuous batching.
+
+    backend must provide
+      bytes_for(req) -> int           device bytes the request holds in flight
+      launch(tickets, stream) -> h    enqueue the batch, return a handle
+      poll(h) -> bool                 True once the device work is complete
+      collect(h) -> list              one result per ticket, in order
+    """
+
+    def __init__(self, backend, hbm_budget_bytes: int, max_inflight: int = 1024,
+                 n_streams: int = 2, max_batch: int = 512):
+        self.backend = backend
+        self.budget = int(hbm_budget_bytes)
+        self.max_inflight = int(max_inflight)
+        self.n_streams = int(n_streams)
+        self.max_batch = int(max_batch)
+        self.queue: collections.deque = collections.deque()
+        self.inflight: List[tuple] = []        # (handle, tickets)
+        self.used_bytes = 0
+        self.used_slots = 0
+        self.next_stream = 0
+        self.completed: List[Ticket] = []
+        self.batches = 0
+        self._lock = threading.Lock()
+
+    # ------------------------------------------------------------ client side
+    def submit(self, req: Request) -> Ticket:
+        nbytes = int(self.backend.bytes_for(req))
+        t = Ticket(req, nbytes)
+        if nbytes > self.budget:
+            t._finish(error=RequestRejected(
+                f"request needs {nbytes} bytes, more than the whole budget {self.budget}"))
+            return t
+        with self._lock:
+            self.queue.append(t)
+        return t
+
+    def cancel(self, ticket: Ticket) -> bool:
+        """Removes a request that has not been admitted yet."""
+        with self._lock:
+            try:
+                self.queue.remove(ticket)
+            except ValueError:
+                return False
+        ticket._finish(error=RequestRejected("cancelled"))
+        return True
+
+    # ------------------------------------------------------------ scheduler
+    def _complete(self) -> int:
+        n = 0
+        still = []
+        for h, tickets in self.inflight:
+            if self.backend.poll(h):
+                try:
+                    results = self.backend.collect(h)
+                    for t, r in zip(tickets, results):
+                        t._finish(result=r)
+                except BaseException as e:   # the batch failed: fail its requests only
+                    for t in tickets:
+                        if not t.done():
+                            t._finish(error=e)
+                for t in tickets:
+                    self.used_bytes -= t.nbytes
+                    self.used_slots -= 1
+                    self.completed.append(t)
+                n += len(tickets)
+            else:
+                still.append((h, tickets))
+        self.inflight = still
+        return n
+
+    def _admit(self) -> List[Ticket]:
+        batch: List[Ticket] = []
+        with self._lock:
+            while self.queue and len(batch) < self.max_batch:
+                t = self.queue[0]
+                if self.used_slots + 1 > self.max_inflight:
+                    break
+                if self.used_bytes + t.nbytes > self.budget:
+                    break
+                self.queue.popleft()
+                self.used_bytes += t.nbytes
+                self.used_slots += 1
+                batch.append(t)
+        return batch
+
+    def tick(self) -> int:
+        """One scheduling round; returns the number of requests completed."""
+        n = self._complete()
+        batch = self._admit()
+        if batch:
+            stream = self.next_stream
+            self.next_stream = (self.next_stream + 1) % self.n_streams
+            try:
+                h = self.backend.launch(batch, stream)
+                self.inflight.append((h, batch))
+                self.batches += 1
+            except BaseException as e:
+                for t in batch:
+                    self.used_bytes -= t.nbytes
+                    self.used_slots -= 1
+                    t._finish(error=e)
+                    self.completed.append(t)
+        return n
+
+    def pending(self) -> int:
+        with self._lock:
+            return len(self.queue) + sum(len(t) for _, t in self.inflight)
+
+    def run_until_idle(self, idle_sleep: float = 0.0):
+        while self.pending():
+            self.tick()
+            if idle_sleep:
+                time.sleep(idle_sleep)
+
+
+# ---------------------------------------------------------------- GPU backend
+
+class GpuBackend:
+    """Runs batches on the GPU through libdrr (plans and the fused NCC call)."""
+
+    def __init__(self, volumes: Dict[str, Any], n_streams: int = 2, max_items: int = 2048,
+                 autotune_items=None):
+        import torch
+        from .plan import Plan
+        self.torch = torch
+        self.names = list(volumes)
+        self.volumes = volumes
+        self.index = {n: i for i, n in enumerate(self.names)}
+        self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
+        self.plan = Plan([volumes[n] for n in self.names], max_items=max_items, use_graph=False)
+        self.dev = volumes[self.names[0]].device
+
+    def bytes_for(self, req: Request) -> int:
+        from . import _lib
+        from .drr import Detector
+        px = req.height * req.width * 4
+        if req.kind == FWD:
+            return px + 64
+        det = Detector(req.height, req.width, req.delta_x, req.delta_y)
+        ws = _lib.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), 1)
+        return 2 * px + ws + 64
+
+    def launch(self, tickets: List[Ticket], stream_idx: int):
+        torch = self.torch
+        from . import _lib
+        from .drr import Detector, _stream
+        from .plan import Item
+        stream = self.streams[stream_idx]
+        stream.wait_stream(torch.cuda.current_stream())
+        n = len(tickets)
+        host = torch.empty((n, 7), dtype=torch.float32, pin_memory=True)
+        host.numpy()[:] = np.stack([np.asarray(t.request.pose, np.float32) for t in tickets])
+        out = {}
+        with torch.cuda.stream(stream):
+            poses = host.to(self.dev, non_blocking=True)
+            items, fwd_idx = [], []
+            groups = collections.defaultdict(list)
+            for k, t in enumerate(tickets):
+                r = t.request
+                det = Detector(r.height, r.width, r.delta_x, r.delta_y)
+                if r.kind == FWD:
+                    img = torch.empty((r.height, r.width), dtype=torch.float32, device=self.dev)
+                    items.append(Item(self.index[r.volume], det, poses[k], img))
+                    fwd_idx.append(k)
+                    out[k] = img
+                else:
+                    groups[(r.volume, r.height, r.width, r.delta_x, r.delta_y)].append(k)
+            if items:
+                self.plan.execute(items)
+            for (vname, H, W, dx, dy), ks in groups.items():
+                det = Detector(H, W, dx, dy)
+                g = len(ks)
+                idx = torch.tensor(ks, device=self.dev)
+                gp = poses.index_select(0, idx).contiguous()
+                tg = torch.stack([tickets[k].request.target.reshape(H, W) for k in ks]).contiguous()
+                loss = torch.empty((g,), dtype=torch.float32, device=self.dev)
+                grad = torch.empty((g, 7), dtype=torch.float32, device=self.dev)
+                img = torch.empty((g, H, W), dtype=torch.float32, device=self.dev)
+                nb = _lib.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), g)
+                ws = torch.empty(max(nb, 8), dtype=torch.uint8, device=self.dev)
+                vol = self.volumes[vname]
+                _lib.call("drr_render_ncc_grad", vol.packed.data_ptr(), ctypes.byref(vol.desc),
+                          ctypes.byref(det.desc), gp.data_ptr(), g, tg.data_ptr(), H * W,
+                          img.data_ptr(), loss.data_ptr(), grad.data_ptr(), ws.data_ptr(),
+                          ws.numel(), _stream())
+                for j, k in enumerate(ks):
+                    out[k] = (img[j], loss[j], grad[j])
+            ev = torch.cuda.Event()
+            ev.record(stream)
+        return (ev, out, n, host)
+
+    def poll(self, h) -> bool:
+        return h[0].query()
+
+    def collect(self, h):
+        ev, out, n, _ = h
+        return [out[k] for k in range(n)]
+
+
+def plain_forward(volumes: Dict[str, Any], req: Request):
+    """Comparison path: one request, one plain drr_render call, synchronous."""
+    import torch
+    from .drr import Detector, render
+    det = Detector(req.height, req.width, req.delta_x, req.delta_y)
+    pose = torch.from_numpy(np.asarray(req.pose, np.float32)).to(volumes[req.volume].device)
+    return render(volumes[req.volume], pose[None], det)[0]

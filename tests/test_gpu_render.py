@@ -198,3 +198,26 @@ def test_ct512_full_image_one_pose(ct512):
     assert_image_close(img.cpu().numpy(), ref)
     d = np.abs(cnt.cpu().numpy().astype(np.int64) - rcnt)
     assert d.max() <= 1 and (d == 0).mean() > 0.999
+
+
+def test_layouts_render_identically(small, ct512):
+    """The per-axis copies only change memory order: renders are bitwise equal
+    to the single-copy layout, for poses whose central ray runs along x, y
+    and z."""
+    P = _lib_objs()
+    for ph, _, _ in (small, ct512):
+        v_in = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV,
+                        layout="input")
+        v_ax = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV,
+                        layout="per_axis")
+        assert v_ax.nbytes == 3 * v_in.nbytes
+        base = random_poses(6, 0.3, 5.0, 1000.0, seed=31)
+        base[2:4, 0] += math.pi / 2          # central ray along y
+        base[4:6, 1] += math.pi / 2          # central ray along z
+        det = P.Detector(48, 40, 3.0, 3.0)
+        a = P.render(v_in, _gpu(base), det)
+        b = P.render(v_ax, _gpu(base), det)
+        assert torch.equal(a, b)
+        ia, ja = P.render(v_in, _gpu(base), det, jacobian=True)
+        ib, jb = P.render(v_ax, _gpu(base), det, jacobian=True)
+        assert torch.equal(ja, jb)
