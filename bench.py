@@ -47,6 +47,14 @@ def parse():
                     help="approximate CPU time (thread-seconds) for the oracle sample")
     ap.add_argument("--only", choices=["fwd", "fwdbwd", "direct"], default=None,
                     help="time one phase only (for profiling runs)")
+    ap.add_argument("--mode", choices=["drr", "register", "serve"], default="drr",
+                    help="drr: the headline forward / fwd+bwd batch (default); register: "
+                         "32 batched registrations; serve: the request loop over four "
+                         "resident volumes at a QPS sweep")
+    ap.add_argument("--requests", type=int, default=2000,
+                    help="requests per QPS point in --mode serve")
+    ap.add_argument("--tune-cache", default=None,
+                    help="autotuner cache file (reuse a launch-shape choice across runs)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="run only a plain 1 GiB device-to-device copy (reference kernel "
                          "for scaling hardware byte counters)")
@@ -96,8 +104,9 @@ def profiled_traffic(plan_cfg):
     rec = json.loads(m.group(1))
     if rec.get("source_digest") != _source_digest():
         return None
-    if rec.get("tile_code") != plan_cfg["tile_code"] or rec.get("wg_per_cu") != plan_cfg["wg_per_cu"]:
-        return None
+    for k in ("strategy", "tile_code", "wg_per_cu"):
+        if rec.get(k) != plan_cfg[k]:
+            return None
     return rec.get("traffic_bytes_per_launch")
 
 
@@ -120,6 +129,179 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
                       f"{dt:.2f} s wall on {nthreads} threads"}
 
 
+def bench_register(args):
+    """32 registration problems on the 512 x 512 x 133 CT, 256 x 256
+    detector: ground-truth poses (angles +-pi/6, shifts +-30 mm), starts
+    offset by up to 15 deg / 25 mm per parameter, 200 steps of momentum
+    gradient descent on -ZNCC with the step sizes of Sec. 3.2, all problems
+    in one captured graph; beside it the one-DRR-at-a-time autograd path."""
+    import torch
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.register import (BatchedRegistration, CONVERGED_LOSS,
+                                               default_rates, pose_errors,
+                                               register_one_at_a_time)
+    from synth import make_phantom, random_poses
+
+    n, steps = 32, 200
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
+    det = P.Detector(256, 256, 1.4, 1.4)
+    gt = random_poses(n, math.pi / 6, 30.0, 1020.0, seed=11)
+    rng = np.random.default_rng(12)
+    off = np.zeros((n, 7), np.float32)
+    off[:, :3] = rng.uniform(-1, 1, (n, 3)) * math.radians(15.0)
+    off[:, 3:6] = rng.uniform(-1, 1, (n, 3)) * 25.0
+    targets = P.render(vol, torch.from_numpy(gt).cuda(), det)
+    init = torch.from_numpy(gt + off).cuda()
+    rates = default_rates(n)
+    reg = BatchedRegistration(vol, det, targets, init, rates, steps=steps, use_graph=True)
+    reg.run()                                     # capture + first replay
+    torch.cuda.synchronize()
+    walls = []
+    for _ in range(max(args.steps // 4, 3)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        a.record()
+        poses, hist = reg.run()
+        b.record()
+        torch.cuda.synchronize()
+        walls.append(a.elapsed_time(b) / 1e3)
+    t_batch = float(np.median(walls))
+    h = hist.cpu().numpy()
+    r_err, t_err = pose_errors(poses.cpu().numpy(), gt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    po, fl = register_one_at_a_time(vol, det, targets, init, rates, steps=steps)
+    torch.cuda.synchronize()
+    t_one = time.perf_counter() - t0
+    r1, t1 = pose_errors(po.cpu().numpy(), gt)
+    fl = fl.cpu().numpy()
+    r0, t0e = pose_errors(gt + off, gt)
+    res = {"metric": "batched registration: wall time and final pose error", "mode": "register",
+           "problems": n, "steps": steps, "detector": [256, 256],
+           "volume": [512, 512, 133], "rates": {"rot": float(rates[0, 0]), "xyz": float(rates[0, 3])},
+           "initial_error_mean": {"rot_deg": float(r0.mean()), "trans_mm": float(t0e.mean())},
+           "batched_graph": {"wall_s": t_batch, "ms_per_step": 1e3 * t_batch / steps,
+                             "fwdbwd_drrs_per_s": n * (steps + 1) / t_batch,
+                             "converged": int((h[-1] < CONVERGED_LOSS).sum()),
+                             "final_loss_mean": float(h[-1].mean()),
+                             "rot_err_deg_median": float(np.median(r_err)),
+                             "trans_err_mm_median": float(np.median(t_err)),
+                             "rot_err_deg_mean": float(r_err.mean()),
+                             "trans_err_mm_mean": float(t_err.mean())},
+           "one_at_a_time": {"wall_s": t_one, "converged": int((fl < CONVERGED_LOSS).sum()),
+                             "rot_err_deg_median": float(np.median(r1)),
+                             "trans_err_mm_median": float(np.median(t1))},
+           "speedup": t_one / t_batch, "data": "synthetic"}
+    print(json.dumps(res), flush=True)
+
+
+def bench_serve(args):
+    """The request loop over four resident volumes (128^3 at 2 mm, 256^3 at
+    1 mm, 512 x 512 x 133, 512 x 512 x 300 at 0.7 x 0.7 x 1.25 mm): requests
+    with a random volume, a detector of 128^2 / 200^2 / 256^2 / 512^2 pixels
+    (pitch 358.4 mm / N, SDD 1020 mm), a random pose and a 70/30 split of
+    forward vs forward + backward (NCC gradient against a target rendered
+    near the pose), Poisson arrivals at a sweep of offered rates."""
+    import torch
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.serve import (FWD, FWDBWD, GpuBackend, Request, Server,
+                                            plain_forward)
+    from synth import make_phantom, random_poses
+
+    dev = "cuda"
+    names = ["ct128", "ct256", "ct512", "ct512x300"]
+    vols = {}
+    for nm in names:
+        print(f"[bench] phantom {nm}", file=sys.stderr, flush=True)
+        ph = make_phantom(nm, seed=0)
+        vols[nm] = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=dev)
+    sizes = [128, 200, 256, 512]
+    rng = np.random.default_rng(7)
+    # a pool of targets per (volume, detector) for the forward + backward requests
+    pool = {}
+    for nm in names:
+        for N in sizes:
+            gt = random_poses(4, math.pi / 6, 30.0, 1020.0, seed=10 * names.index(nm) + sizes.index(N))
+            det = P.Detector(N, N, 358.4 / N, 358.4 / N)
+            pool[(nm, N)] = (gt, P.render(vols[nm], torch.from_numpy(gt).to(dev), det))
+
+    def make_requests(count, seed):
+        r = np.random.default_rng(seed)
+        out = []
+        for i in range(count):
+            nm = names[int(r.integers(0, 4))]
+            N = sizes[int(r.integers(0, 4))]
+            if r.uniform() < 0.7:
+                pose = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=seed * 100003 + i)[0]
+                out.append(Request(nm, N, N, 358.4 / N, 358.4 / N, pose, FWD))
+            else:
+                gt, tg = pool[(nm, N)]
+                k = int(r.integers(0, 4))
+                pose = gt[k].copy()
+                pose[:3] += r.uniform(-1, 1, 3).astype(np.float32) * 0.05
+                pose[3:6] += r.uniform(-1, 1, 3).astype(np.float32) * 5.0
+                out.append(Request(nm, N, N, 358.4 / N, 358.4 / N, pose, FWDBWD, tg[k]))
+        return out
+
+    budget = 2 << 30
+
+    def run_point(reqs, qps):
+        be = GpuBackend(vols, n_streams=3)
+        srv = Server(be, hbm_budget_bytes=budget, n_streams=3, max_batch=256)
+        if qps is None:
+            arrivals = np.zeros(len(reqs))
+        else:
+            arrivals = np.cumsum(rng.exponential(1.0 / qps, len(reqs)))
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        tickets, k = [], 0
+        while k < len(reqs) or srv.pending():
+            now = time.perf_counter() - t0
+            while k < len(reqs) and arrivals[k] <= now:
+                reqs[k].arrival = t0 + arrivals[k]
+                tickets.append(srv.submit(reqs[k]))
+                k += 1
+            srv.tick()
+        torch.cuda.synchronize()
+        wall = time.perf_counter() - t0
+        lat = np.array([t.latency for t in tickets]) * 1e3
+        return {"offered_qps": qps, "achieved_rps": len(reqs) / wall,
+                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+                "batches": srv.batches}
+
+    print("[bench] serving: saturation", file=sys.stderr, flush=True)
+    warm = make_requests(200, seed=1)
+    run_point(warm, None)
+    sat = run_point(make_requests(args.requests, seed=2), None)
+    points = []
+    for frac in (0.1, 0.3, 0.5, 0.7, 0.9, 1.1):
+        q = frac * sat["achieved_rps"]
+        print(f"[bench] serving at {q:.0f} req/s", file=sys.stderr, flush=True)
+        pt = run_point(make_requests(args.requests, seed=int(100 * frac) + 3), q)
+        pt["offered_frac_of_saturation"] = frac
+        points.append(pt)
+    # plain single-DRR forward path, one request at a time
+    reqs = [r for r in make_requests(400, seed=9) if r.kind == FWD]
+    lat = []
+    for r in reqs:
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        plain_forward(vols, r)
+        torch.cuda.synchronize()
+        lat.append((time.perf_counter() - t) * 1e3)
+    lat = np.array(lat)
+    res = {"metric": "served requests/s and p50/p99 latency (ms), mixed volumes and detectors",
+           "mode": "serve", "volumes": names, "detectors": sizes, "fwd_fraction": 0.7,
+           "hbm_budget_bytes": budget, "saturation": sat, "sweep": points,
+           "plain_single_drr_forward": {"rps": float(1e3 / lat.mean()),
+                                        "p50_ms": float(np.percentile(lat, 50)),
+                                        "p99_ms": float(np.percentile(lat, 99)),
+                                        "requests": len(lat)},
+           "data": "synthetic"}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -129,6 +311,12 @@ def main():
         sys.exit(2)
     if args.copy_calibration:
         copy_calibration()
+        return
+    if args.mode == "register":
+        bench_register(args)
+        return
+    if args.mode == "serve":
+        bench_serve(args)
         return
 
     import torch
@@ -176,7 +364,8 @@ def main():
     from paper_2208_12737_amd.plan import Item, Plan
     items = [Item(0, det, poses[b], img[b]) for b in range(nb)]
     print("[bench] autotuning the batched plan", file=sys.stderr, flush=True)
-    plan = Plan([vol], max_items=nb, use_graph=True, autotune=True, tune_items=items)
+    plan = Plan([vol], max_items=nb, use_graph=True, autotune=True, tune_items=items,
+                cache_path=args.tune_cache)
     plan_cfg = plan.config
 
     def fwd():
@@ -256,8 +445,8 @@ def main():
         res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "traffic": profiled_traffic(plan_cfg),
-                           "kernel": f"render_persistent (image mode, tile code "
-                                     f"{plan_cfg['tile_code']}, {plan_cfg['wg_per_cu']} WG/CU)",
+                           "kernel": f"{plan_cfg['strategy']} plan kernel, image mode, tile "
+                                     f"code {plan_cfg['tile_code']}, {plan_cfg['wg_per_cu']} WG/CU",
                            "bytes_per_launch": bytes_fwd}
         res["plan"] = plan_cfg
     if "direct" in times:

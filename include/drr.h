@@ -215,9 +215,17 @@ typedef struct drr_plan_desc {
     int32_t use_graph;                   /* 1: capture the launch in a HIP graph */
     int32_t autotune;                    /* 1: time candidate launch shapes at create */
     const char* tune_cache_path;         /* NULL or a file for autotune results */
+    int32_t strategy;                    /* without autotune: DRR_PLAN_* (-1 = default) */
     int32_t tile_code;                   /* without autotune: launch shape (-1 = default) */
     int32_t wg_per_cu;                   /* without autotune: workgroups per CU (0 = max) */
 } drr_plan_desc;
+
+/* Plan strategies: a persistent grid sized to the GPU whose workgroups pull
+ * tiles from per-XCD device queues (one graph serves any batch), or one
+ * workgroup per tile (the graph is re-captured when the tile count of a
+ * batch changes). */
+#define DRR_PLAN_PERSISTENT 0
+#define DRR_PLAN_FLAT 1
 
 typedef struct drr_plan drr_plan;
 
@@ -233,9 +241,9 @@ int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_ite
 int32_t drr_plan_execute(drr_plan* plan, const drr_work_item* items, int32_t n_items,
                          void* stream);
 
-/* Chosen launch shape: tile code and workgroups per CU (for reports). */
-int32_t drr_plan_config(const drr_plan* plan, int32_t* tile_code, int32_t* wg_per_cu,
-                        int32_t* use_graph);
+/* Chosen launch: strategy, tile code and workgroups per CU (for reports). */
+int32_t drr_plan_config(const drr_plan* plan, int32_t* strategy, int32_t* tile_code,
+                        int32_t* wg_per_cu, int32_t* use_graph);
 
 void drr_plan_destroy(drr_plan* plan);
 

@@ -21,6 +21,8 @@ DRR_EHIP = -3
 DRR_ENOTSUP = -4
 DRR_ITEM_JAC = 1
 DRR_ITEM_COUNT = 2
+DRR_PLAN_PERSISTENT = 0
+DRR_PLAN_FLAT = 1
 
 
 class DrrError(RuntimeError):
@@ -50,8 +52,8 @@ class PlanDesc(ctypes.Structure):
     _fields_ = [("max_items", ctypes.c_int32), ("n_volumes", ctypes.c_int32),
                 ("volumes", ctypes.POINTER(VolumeDesc)), ("packed", ctypes.POINTER(ctypes.c_void_p)),
                 ("use_graph", ctypes.c_int32), ("autotune", ctypes.c_int32),
-                ("tune_cache_path", ctypes.c_char_p), ("tile_code", ctypes.c_int32),
-                ("wg_per_cu", ctypes.c_int32)]
+                ("tune_cache_path", ctypes.c_char_p), ("strategy", ctypes.c_int32),
+                ("tile_code", ctypes.c_int32), ("wg_per_cu", ctypes.c_int32)]
 
 
 _V = ctypes.c_void_p
@@ -81,7 +83,7 @@ SIGNATURES = {
                                ctypes.POINTER(_V)]),
     "drr_plan_execute": (_I32, [_V, ctypes.POINTER(WorkItem), _I32, _V]),
     "drr_plan_config": (_I32, [_V, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
-                               ctypes.POINTER(_I32)]),
+                               ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "drr_plan_destroy": (None, [_V]),
     "drr_set_launch_occupancy": (_I32, [_I32]),
     "drr_status_string": (ctypes.c_char_p, [_I32]),

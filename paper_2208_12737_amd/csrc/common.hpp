@@ -135,4 +135,23 @@ inline DetArgs det_args(const drr_detector_desc& d)
 
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// Dynamic LDS to reserve per workgroup so that at most `wg_per_cu`
+// workgroups are resident on a CU (0 = no limit).
+inline size_t occupancy_lds(int wg_per_cu)
+{
+    static int lds_per_cu = -1;
+    if (lds_per_cu < 0) {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
+                hipSuccess || v <= 0)
+            v = 160 * 1024;
+        lds_per_cu = v;
+    }
+    if (wg_per_cu <= 0) return 0;
+    // a little below the share so that the kernel's static LDS still fits
+    size_t share = (size_t)lds_per_cu / (size_t)wg_per_cu;
+    return share > 1024 ? share - 1024 : 0;
+}
+
 }  // namespace drr

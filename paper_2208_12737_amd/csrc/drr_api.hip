@@ -45,23 +45,6 @@ static int wg_per_cu_for(const drr_volume_desc& vol)
     return vol.layout == DRR_LAYOUT_PER_AXIS ? 6 : 4;
 }
 
-static size_t occupancy_lds(int wg_per_cu)
-{
-    static int lds_per_cu = -1;
-    if (lds_per_cu < 0) {
-        int dev = 0, v = 0;
-        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
-        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
-                hipSuccess || v <= 0)
-            v = 160 * 1024;
-        lds_per_cu = v;
-    }
-    if (wg_per_cu <= 0) return 0;
-    // a little below the share so that the static LDS of the kernel still fits
-    size_t share = (size_t)lds_per_cu / (size_t)wg_per_cu;
-    return share > 1024 ? share - 1024 : 0;
-}
-
 struct FlatGrid {
     int tiles_x, tiles_y, wg_per_pose;
 };

@@ -17,6 +17,7 @@
 
 #include <chrono>
 #include <map>
+#include <algorithm>
 #include <mutex>
 #include <string>
 #include <vector>
@@ -57,7 +58,7 @@ struct Slot {
     int32_t* d_counters = nullptr;    // [kPlanModes][kXcds]
     hipEvent_t done = nullptr;
     bool used = false;
-    std::map<int, hipGraphExec_t> graphs;   // by mode mask
+    std::map<std::vector<int>, hipGraphExec_t> graphs;   // by mode mask (+ flat grids)
 };
 
 // ------------------------------------------------------------------ kernels
@@ -123,6 +124,36 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
     (void)sizeof(S);
 }
 
+// Flat strategy: one workgroup per tile (grid = the group's tile count), the
+// hardware dispatcher as the queue, with the XCD-aware ordering of the
+// direct launches.  No atomics; the grid size is fixed per execute.
+template <int TW, int WX, int WY, int MODE>
+__global__ __launch_bounds__(64 * WX * WY) void render_plan_flat(const char* __restrict__ block,
+                                                                 int group)
+{
+    __shared__ double lds[1];
+    const PlanHeader* hdr = (const PlanHeader*)block;
+    const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
+    const int first = hdr->first[group], count = hdr->count[group];
+    const int t = (int)xcd_logical(blockIdx.x, gridDim.x);
+    int lo = 0, hi = count - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[first + mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    const PlanItem& it = items[first + lo];
+    const int local = t - it.tile_begin;
+    const int ty = local / it.tiles_x, tx = local % it.tiles_x;
+    TileOut o;
+    o.image = it.image;
+    o.jac = it.jac;
+    o.counts = it.counts;
+    o.aux = nullptr;
+    o.partial = nullptr;
+    render_tile<TW, WX, WY, MODE>(it.vol, it.det, it.pose, tx, ty, o, lds);
+}
+
 // ------------------------------------------------------------------ shapes
 
 // Candidate launch shapes: wave tile width (pixels) and waves per workgroup.
@@ -167,6 +198,33 @@ static PersistentFn kernel_for(int mode, int code)
     return persistent_fn<kJac>(code);
 }
 
+typedef void (*FlatFn)(const char*, int);
+
+template <int MODE>
+static FlatFn flat_fn(int code)
+{
+    switch (code) {
+    case 0: return render_plan_flat<8, 2, 2, MODE>;
+    case 1: return render_plan_flat<8, 1, 1, MODE>;
+    case 2: return render_plan_flat<8, 1, 4, MODE>;
+    case 3: return render_plan_flat<16, 1, 4, MODE>;
+    case 4: return render_plan_flat<4, 4, 1, MODE>;
+    case 5: return render_plan_flat<8, 4, 1, MODE>;
+    case 6: return render_plan_flat<4, 1, 4, MODE>;
+    case 7: return render_plan_flat<2, 2, 2, MODE>;
+    default: return render_plan_flat<1, 4, 1, MODE>;
+    }
+}
+
+static FlatFn flat_kernel_for(int mode, int code)
+{
+    if (mode == kImage) return flat_fn<kImage>(code);
+    if (mode == kCount) return flat_fn<kCount>(code);
+    return flat_fn<kJac>(code);
+}
+
+enum Strategy { kPersistent = 0, kFlat = 1 };
+
 static int mode_of_flags(int32_t flags)
 {
     if (flags & DRR_ITEM_JAC) return kJac;
@@ -182,9 +240,10 @@ struct drr_plan {
     int max_items = 0;
     std::vector<drr_volume_desc> vols;
     std::vector<const void*> packed;
+    int strategy = 0;          // kPersistent or kFlat
     int tile_code = 0;
     int wg_per_cu = 0;         // requested workgroups per CU (0 = occupancy limit)
-    int grid[kPlanModes] = {0, 0, 0};
+    int grid[kPlanModes] = {0, 0, 0};   // persistent grid per mode
     int num_cus = 0;
     bool use_graph = false;
     Slot slots[kRing];
@@ -256,10 +315,20 @@ static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
 {
     const ShapeInfo& sh = kShapes[p->tile_code];
     const int threads = 64 * sh.wx * sh.wy;
+    int32_t rc;
+    if (p->strategy == kFlat) {
+        const size_t lds = occupancy_lds(p->wg_per_cu);
+        for (int m = 0; m < kPlanModes; ++m) {
+            if (!(mask & (1 << m))) continue;
+            hipLaunchKernelGGL(flat_kernel_for(m, p->tile_code), dim3(s.h_header->tiles[m]),
+                               dim3(threads), lds, st, (const char*)s.d_block, m);
+            if ((rc = check_launch("plan flat kernel"))) return rc;
+        }
+        return DRR_OK;
+    }
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, s.d_counters,
                        kPlanModes * kXcds);
-    int32_t rc = check_launch("plan counter reset");
-    if (rc) return rc;
+    if ((rc = check_launch("plan counter reset"))) return rc;
     for (int m = 0; m < kPlanModes; ++m) {
         if (!(mask & (1 << m))) continue;
         hipLaunchKernelGGL(kernel_for(m, p->tile_code), dim3(p->grid[m]), dim3(threads), 0, st,
@@ -290,7 +359,10 @@ static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hi
     hipError_t e = hipMemcpyAsync(s.d_block, s.h_header, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(DRR_EHIP, "plan table copy: %s", hipGetErrorString(e));
     if (p->use_graph && st != nullptr) {
-        auto found = s.graphs.find(mask);
+        std::vector<int> key = {mask};
+        if (p->strategy == kFlat)
+            for (int m = 0; m < kPlanModes; ++m) key.push_back(s.h_header->tiles[m]);
+        auto found = s.graphs.find(key);
         if (found == s.graphs.end()) {
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
@@ -303,7 +375,7 @@ static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hi
             e = hipGraphInstantiate(&ge, g, nullptr, nullptr, 0);
             (void)hipGraphDestroy(g);
             if (e != hipSuccess) return fail(DRR_EHIP, "graph instantiate: %s", hipGetErrorString(e));
-            found = s.graphs.emplace(mask, ge).first;
+            found = s.graphs.emplace(key, ge).first;
         }
         e = hipGraphLaunch(found->second, st);
         if (e != hipSuccess) return fail(DRR_EHIP, "graph launch: %s", hipGetErrorString(e));
@@ -342,7 +414,7 @@ static int32_t validate_items(const drr_plan* p, const drr_work_item* items, int
 
 static std::string tune_key(const drr_plan* p, const drr_work_item* items, int n)
 {
-    std::string k = "v1";
+    std::string k = "v2";
     for (const auto& v : p->vols) {
         char b[96];
         snprintf(b, sizeof b, "|%dx%dx%d@%.3g,%.3g,%.3g", v.nx, v.ny, v.nz, v.spacing[0],
@@ -358,7 +430,8 @@ static std::string tune_key(const drr_plan* p, const drr_work_item* items, int n
     return k + b;
 }
 
-static bool cache_lookup(const char* path, const std::string& key, int* code, int* wpc)
+static bool cache_lookup(const char* path, const std::string& key, int* strategy, int* code,
+                         int* wpc)
 {
     if (!path) return false;
     FILE* f = fopen(path, "r");
@@ -367,9 +440,10 @@ static bool cache_lookup(const char* path, const std::string& key, int* code, in
     bool hit = false;
     while (fgets(line, sizeof line, f)) {
         char k[900];
-        int c, w;
-        if (sscanf(line, "%899s %d %d", k, &c, &w) == 3 && key == k && c >= 0 &&
-            c < kNumShapes && w >= 0) {
+        int g, c, w;
+        if (sscanf(line, "%899s %d %d %d", k, &g, &c, &w) == 4 && key == k &&
+            (g == kPersistent || g == kFlat) && c >= 0 && c < kNumShapes && w >= 0) {
+            *strategy = g;
             *code = c;
             *wpc = w;
             hit = true;
@@ -379,12 +453,13 @@ static bool cache_lookup(const char* path, const std::string& key, int* code, in
     return hit;
 }
 
-static void cache_store(const char* path, const std::string& key, int code, int wpc)
+static void cache_store(const char* path, const std::string& key, int strategy, int code,
+                        int wpc)
 {
     if (!path) return;
     FILE* f = fopen(path, "a");
     if (!f) return;
-    fprintf(f, "%s %d %d\n", key.c_str(), code, wpc);
+    fprintf(f, "%s %d %d %d\n", key.c_str(), strategy, code, wpc);
     fclose(f);
 }
 
@@ -416,36 +491,42 @@ static int32_t autotune(drr_plan* p, const drr_work_item* items, int n, hipStrea
                         const char* cache)
 {
     const std::string key = tune_key(p, items, n);
-    int code = 0, wpc = 0;
-    if (cache_lookup(cache, key, &code, &wpc)) {
+    int strategy = 0, code = 0, wpc = 0;
+    if (cache_lookup(cache, key, &strategy, &code, &wpc)) {
+        p->strategy = strategy;
         p->tile_code = code;
         p->wg_per_cu = wpc;
         return compute_grids(p);
     }
     float best = 1e30f;
-    int best_code = 0, best_wpc = 0;
+    int best_code = 0, best_wpc = 0, best_strategy = kPersistent;
     // resident workgroups per CU: the register limit, or fewer (less cache
     // pressure from concurrent rays)
     const int wpcs[] = {0, 3, 4, 5, 6};
-    for (int c = 0; c < kNumShapes; ++c) {
-        for (int w : wpcs) {
-            p->tile_code = c;
-            p->wg_per_cu = w;
-            for (Slot& s : p->slots) drop_graphs(s);
-            float ms = 0.0f;
-            int32_t rc = time_config(p, items, n, st, &ms);
-            if (rc) return rc;
-            if (ms < best) {
-                best = ms;
-                best_code = c;
-                best_wpc = w;
+    for (int strat = kPersistent; strat <= kFlat; ++strat) {
+        for (int c = 0; c < kNumShapes; ++c) {
+            for (int w : wpcs) {
+                p->strategy = strat;
+                p->tile_code = c;
+                p->wg_per_cu = w;
+                for (Slot& s : p->slots) drop_graphs(s);
+                float ms = 0.0f;
+                int32_t rc = time_config(p, items, n, st, &ms);
+                if (rc) return rc;
+                if (ms < best) {
+                    best = ms;
+                    best_code = c;
+                    best_wpc = w;
+                    best_strategy = strat;
+                }
             }
         }
     }
     for (Slot& s : p->slots) drop_graphs(s);
+    p->strategy = best_strategy;
     p->tile_code = best_code;
     p->wg_per_cu = best_wpc;
-    cache_store(cache, key, best_code, best_wpc);
+    cache_store(cache, key, best_strategy, best_code, best_wpc);
     return compute_grids(p);
 }
 
@@ -509,7 +590,12 @@ int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_ite
             free_plan(p);
             return fail(DRR_EINVAL, "plan_create: tile_code must be < %d", kNumShapes);
         }
-        p->tile_code = desc->tile_code >= 0 ? desc->tile_code : 0;
+        if (desc->strategy > kFlat) {
+            free_plan(p);
+            return fail(DRR_EINVAL, "plan_create: unknown strategy %d", desc->strategy);
+        }
+        p->strategy = desc->strategy >= 0 ? desc->strategy : kFlat;
+        p->tile_code = desc->tile_code >= 0 ? desc->tile_code : 2;
         p->wg_per_cu = desc->wg_per_cu > 0 ? desc->wg_per_cu : 0;
     }
     int32_t rc = compute_grids(p);
@@ -539,10 +625,11 @@ int32_t drr_plan_execute(drr_plan* plan, const drr_work_item* items, int32_t n_i
     return execute_locked(plan, items, n_items, as_stream(stream));
 }
 
-int32_t drr_plan_config(const drr_plan* plan, int32_t* tile_code, int32_t* wg_per_cu,
-                        int32_t* use_graph)
+int32_t drr_plan_config(const drr_plan* plan, int32_t* strategy, int32_t* tile_code,
+                        int32_t* wg_per_cu, int32_t* use_graph)
 {
     if (!plan) return fail(DRR_EINVAL, "plan_config: NULL plan");
+    if (strategy) *strategy = plan->strategy;
     if (tile_code) *tile_code = plan->tile_code;
     if (wg_per_cu) *wg_per_cu = plan->wg_per_cu;
     if (use_graph) *use_graph = plan->use_graph ? 1 : 0;

@@ -60,7 +60,8 @@ class Plan:
 
     def __init__(self, volumes: Sequence[Volume], max_items: int = 1024, use_graph: bool = True,
                  autotune: bool = False, tune_items: Optional[Sequence[Item]] = None,
-                 cache_path: Optional[str] = None, tile_code: int = -1, wg_per_cu: int = 0):
+                 cache_path: Optional[str] = None, strategy: int = -1, tile_code: int = -1,
+                 wg_per_cu: int = 0):
         self.volumes = list(volumes)
         self._descs = (_lib.VolumeDesc * len(self.volumes))(*[v.desc for v in self.volumes])
         self._packed = (ctypes.c_void_p * len(self.volumes))(
@@ -74,6 +75,7 @@ class Plan:
         d.autotune = 1 if autotune else 0
         self._cache = cache_path.encode() if cache_path else None
         d.tune_cache_path = self._cache
+        d.strategy = strategy
         d.tile_code = tile_code
         d.wg_per_cu = wg_per_cu
         self._desc = d
@@ -92,9 +94,11 @@ class Plan:
 
     @property
     def config(self):
-        t, w, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
-        _lib.call("drr_plan_config", self._h, ctypes.byref(t), ctypes.byref(w), ctypes.byref(g))
-        return {"tile_code": t.value, "wg_per_cu": w.value, "use_graph": bool(g.value)}
+        s, t, w, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
+        _lib.call("drr_plan_config", self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(w),
+                  ctypes.byref(g))
+        return {"strategy": "flat" if s.value == _lib.DRR_PLAN_FLAT else "persistent",
+                "tile_code": t.value, "wg_per_cu": w.value, "use_graph": bool(g.value)}
 
     def close(self):
         if getattr(self, "_h", None):

@@ -53,11 +53,12 @@ def _mixed_items(P, vols, seed):
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
-def test_plan_matches_plain_render(vols, use_graph):
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_plan_matches_plain_render(vols, use_graph, strategy):
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.plan import Plan
     vs, grids = vols
-    plan = Plan(vs, max_items=64, use_graph=use_graph)
+    plan = Plan(vs, max_items=64, use_graph=use_graph, strategy=strategy)
     for rep in range(3):            # replays with new poses and outputs
         items = _mixed_items(P, vs, seed=rep)
         plan.execute(items)
@@ -80,11 +81,12 @@ def test_plan_matches_plain_render(vols, use_graph):
     plan.close()
 
 
-def test_plan_is_deterministic(vols):
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_plan_is_deterministic(vols, strategy):
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.plan import Plan
     vs, _ = vols
-    plan = Plan(vs, max_items=64, use_graph=True)
+    plan = Plan(vs, max_items=64, use_graph=True, strategy=strategy)
     a = _mixed_items(P, vs, seed=5)
     b = _mixed_items(P, vs, seed=5)
     plan.execute(a)
