@@ -26,7 +26,9 @@ import os
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+# DRR_ORACLE_LIB may point the tests at another build of drr_oracle.c (used to
+# check that planted mistakes in the oracle make its pins fail).
+_LIB_PATH = os.environ.get("DRR_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)

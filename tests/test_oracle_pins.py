@@ -65,6 +65,14 @@ def test_geometry_special_poses():
     # gamma = pi/2 rolls the detector about the principal axis: u -> v
     _, p = oracle.ray_endpoints([0, 0, math.pi / 2, 0, 0, 0, sdd], 1, 3, 2.0, 2.0, 0, 2)
     np.testing.assert_allclose(p, [-rho, 0, 2.0], atol=1e-9)
+    # two angles fix the order of the factors: with phi = gamma = pi/2,
+    # R e_x = Ry(pi/2) Rx(pi/2) e_x = -e_z and R e_y = Ry(pi/2) e_z = +e_x,
+    # so pixel (0, 2) of a 1 x 3 detector at pitch 2 (u = 2) sits at (2, 0, rho)
+    _, p = oracle.ray_endpoints([0, math.pi / 2, math.pi / 2, 0, 0, 0, sdd], 1, 3, 2.0, 2.0, 0, 2)
+    np.testing.assert_allclose(p, [2.0, 0, rho], atol=1e-9)
+    # and with theta = phi = pi/2 the source sits at R e_x rho = Rz(pi/2)(-e_z) rho
+    s, _ = oracle.ray_endpoints([math.pi / 2, math.pi / 2, 0, 0, 0, 0, sdd], 1, 1, 1.0, 1.0, 0, 0)
+    np.testing.assert_allclose(s, [0, 0, -rho], atol=1e-9)
     # translation moves source and detector together
     s, p = oracle.ray_endpoints([0, 0, 0, 1, 2, 3, sdd], 1, 1, 1.0, 1.0, 0, 0)
     np.testing.assert_allclose(s, [rho + 1, 2, 3], atol=1e-12)
