@@ -15,6 +15,7 @@ Parity status per function:
   trace_rays_grad            pinned (central differences of trace_rays)
   ray_endpoint_derivs        pinned (central differences of ray_endpoints)
   render_jacobian            pinned (central differences of render)
+  render_pitch_jacobian      pinned (central differences of render in the pitch)
   zncc / zncc_grad           pinned (closed forms, invariances, differences)
 """
 
@@ -59,6 +60,7 @@ def _load():
     lib.orc_render_jacobian.argtypes = [_dp, _ip, _dp, _dp, _dp, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
                                         ctypes.c_double, _dp, _dp, ctypes.c_int]
+    lib.orc_render_pitch_jacobian.argtypes = lib.orc_render_jacobian.argtypes
     lib.orc_zncc.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
     lib.orc_zncc.restype = ctypes.c_double
     lib.orc_openmp_max_threads.restype = ctypes.c_int
@@ -159,6 +161,17 @@ def render_jacobian(grid: Grid, poses, H, W, delta_x, delta_y, nthreads=1):
     jac = np.zeros((B, H, W, 7))
     _load().orc_render_jacobian(*grid.args(), _ptr(poses), B, H, W, delta_x, delta_y,
                                 _ptr(img), _ptr(jac), nthreads)
+    return img, jac
+
+
+def render_pitch_jacobian(grid: Grid, poses, H, W, delta_x, delta_y, nthreads=1):
+    """Images [B, H, W] and d image / d (delta_x, delta_y) [B, H, W, 2]."""
+    poses = _d(poses).reshape(-1, 7)
+    B = poses.shape[0]
+    img = np.zeros((B, H, W))
+    jac = np.zeros((B, H, W, 2))
+    _load().orc_render_pitch_jacobian(*grid.args(), _ptr(poses), B, H, W, delta_x, delta_y,
+                                      _ptr(img), _ptr(jac), nthreads)
     return img, jac
 
 

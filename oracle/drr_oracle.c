@@ -470,6 +470,45 @@ void orc_render_jacobian(const double *vol, const int32_t dims[3], const double 
     }
 }
 
+/* Per-pixel derivative of the image with respect to the detector pixel
+ * spacing, jac[b][h][w][0..1] = d image / d (delta_x, delta_y).  The pitch
+ * moves only the pixel: d p / d delta_x = R e_y (w + 1/2 - W/2) and
+ * d p / d delta_y = R e_z (h + 1/2 - H/2); the source does not move. */
+void orc_render_pitch_jacobian(const double *vol, const int32_t dims[3], const double spacing[3],
+                               const double origin[3], const double *poses, int32_t n_poses,
+                               int32_t H, int32_t W, double delta_x, double delta_y,
+                               double *image, double *jac, int nthreads)
+{
+    orc_grid g;
+    grid_from(&g, vol, dims, spacing, origin);
+    int cap = dims[0] + dims[1] + dims[2] + 5;
+    int64_t total = (int64_t)n_poses * H * W;
+#pragma omp parallel num_threads(nthreads > 0 ? nthreads : 1)
+    {
+        crossing *list = (crossing *)malloc(sizeof(crossing) * (size_t)cap);
+#pragma omp for schedule(dynamic, 64)
+        for (int64_t r = 0; r < total; ++r) {
+            int64_t b = r / ((int64_t)H * W);
+            int h = (int)((r / W) % H), w = (int)(r % W);
+            const double *pose = poses + 7 * b;
+            double s[3], p[3], gs[3], gp[3], E, R[9];
+            orc_ray_endpoints(pose, H, W, delta_x, delta_y, h, w, s, p);
+            trace_ray_grad(&g, s, p, list, &E, gs, gp);
+            orc_rotation(pose[0], pose[1], pose[2], -1, R);
+            double ku = w + 0.5 - 0.5 * W, kv = h + 0.5 - 0.5 * H;
+            double jx = 0.0, jy = 0.0;
+            for (int c = 0; c < 3; ++c) {
+                jx += gp[c] * R[3 * c + 1] * ku;
+                jy += gp[c] * R[3 * c + 2] * kv;
+            }
+            image[r] = E;
+            jac[2 * r] = jx;
+            jac[2 * r + 1] = jy;
+        }
+        free(list);
+    }
+}
+
 /* Zero-normalised cross-correlation of two images of n pixels (population
  * standard deviations), and its gradient with respect to the first image. */
 double orc_zncc(const double *I, const double *T, int64_t n, double *grad /*nullable*/)

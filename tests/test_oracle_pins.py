@@ -329,6 +329,30 @@ def test_render_jacobian_vs_central_differences(small_phantom):
             assert err < 1e-6, (j, err)
 
 
+def test_pitch_jacobian_vs_central_differences(small_phantom):
+    """d image / d (pixel pitch) against FP64 central differences of render()
+    in delta_x and delta_y, on pixels whose voxel sequence does not change."""
+    ph = small_phantom
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    pose = np.array([0.2, -0.15, 0.1, 2.0, -3.0, 1.0, 1000.0])
+    H, W, dx, dy = 15, 17, 4.0, 3.5
+    img, jac = oracle.render_pitch_jacobian(grid, pose, H, W, dx, dy)
+    ref, _, h0 = oracle.render(grid, pose, H, W, dx, dy)
+    np.testing.assert_allclose(img, ref, rtol=1e-13, atol=1e-13)
+    e = 1e-6
+    for j, (a, b) in enumerate([((dx + e, dy), (dx - e, dy)), ((dx, dy + e), (dx, dy - e))]):
+        ip, _, hp = oracle.render(grid, pose, H, W, *a)
+        im, _, hm = oracle.render(grid, pose, H, W, *b)
+        fd = (ip - im)[0] / (2 * e)
+        ok = ((hp == h0) & (hm == h0))[0]
+        assert ok.mean() > 0.3
+        scale = np.abs(jac[0, :, :, j]).max()
+        assert np.abs(jac[0, :, :, j][ok] - fd[ok]).max() < 1e-6 * scale
+        # the centre column / row does not move with the pitch
+    np.testing.assert_allclose(jac[0, :, W // 2, 0], 0.0, atol=1e-9)
+    np.testing.assert_allclose(jac[0, H // 2, :, 1], 0.0, atol=1e-9)
+
+
 # ---------------------------------------------------------------- ZNCC
 
 def test_zncc_closed_forms():
