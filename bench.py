@@ -47,10 +47,12 @@ def parse():
                     help="approximate CPU time (thread-seconds) for the oracle sample")
     ap.add_argument("--only", choices=["fwd", "fwdbwd", "direct"], default=None,
                     help="time one phase only (for profiling runs)")
-    ap.add_argument("--mode", choices=["drr", "register", "serve"], default="drr",
+    ap.add_argument("--mode", choices=["drr", "register", "serve", "landscape", "table1"],
+                    default="drr",
                     help="drr: the headline forward / fwd+bwd batch (default); register: "
                          "32 batched registrations; serve: the request loop over four "
-                         "resident volumes at a QPS sweep")
+                         "resident volumes at a QPS sweep; landscape: loss sweeps over "
+                         "random and gridded pose offsets")
     ap.add_argument("--requests", type=int, default=2000,
                     help="requests per QPS point in --mode serve")
     ap.add_argument("--tune-cache", default=os.path.join(
@@ -248,15 +250,19 @@ def bench_serve(args):
         return out
 
     budget = 2 << 30
+    # one backend (streams, plan, warm allocator pools) serves every point
+    be = GpuBackend(vols, n_streams=3)
 
     def run_point(reqs, qps):
-        be = GpuBackend(vols, n_streams=3)
+        import gc
         srv = Server(be, hbm_budget_bytes=budget, n_streams=3, max_batch=256)
         if qps is None:
             arrivals = np.zeros(len(reqs))
         else:
             arrivals = np.cumsum(rng.exponential(1.0 / qps, len(reqs)))
         torch.cuda.synchronize()
+        gc.collect()
+        gc.disable()                     # no collector pauses inside the timed loop
         t0 = time.perf_counter()
         tickets, k = [], 0
         while k < len(reqs) or srv.pending():
@@ -268,6 +274,7 @@ def bench_serve(args):
             srv.tick()
         torch.cuda.synchronize()
         wall = time.perf_counter() - t0
+        gc.enable()
         lat = np.array([t.latency for t in tickets]) * 1e3
         return {"offered_qps": qps, "achieved_rps": len(reqs) / wall,
                 "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
@@ -305,6 +312,180 @@ def bench_serve(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_landscape(args):
+    """Loss-landscape sweep of Sec. 3.2 on the 512 x 512 x 133 CT with a
+    256 x 256 detector: 262 144 random offsets (90 deg for theta and phi,
+    45 deg for gamma, 30 mm per shift, centred on the ground truth) and two
+    129 x 129 grids, each pose one DRR reduced straight to -ZNCC."""
+    import torch
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.landscape import (grid_offsets, radial_monotonicity,
+                                                random_offsets, sweep)
+    from synth import make_phantom, random_poses
+
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
+    det = P.Detector(256, 256, 1.4, 1.4)
+    gt = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=21)[0]
+    n = 262144
+    off = random_offsets(n, seed=22)
+    sweep(vol, det, gt, off[:4096])                     # warm-up
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    loss = sweep(vol, det, gt, off, chunk=8192)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    g1 = sweep(vol, det, gt, grid_offsets(0, 1, math.radians(90), math.radians(90), 129))
+    g2 = sweep(vol, det, gt, grid_offsets(3, 4, 30.0, 30.0, 129))
+    frac, _ = radial_monotonicity(vol, det, gt, n_dirs=256, n_steps=16, radius=0.25)
+    res = {"metric": "loss-landscape poses/s (render + -ZNCC per pose)", "mode": "landscape",
+           "poses": n, "detector": [256, 256], "volume": [512, 512, 133],
+           "poses_per_s": n / dt, "wall_s": dt,
+           "loss_quantiles": [float(q) for q in np.quantile(loss, [0, 0.01, 0.5, 0.99, 1])],
+           "grid_theta_phi": {"argmin_at_centre": bool(np.argmin(g1) == 129 * 64 + 64),
+                              "min": float(g1.min())},
+           "grid_tx_ty": {"argmin_at_centre": bool(np.argmin(g2) == 129 * 64 + 64),
+                          "min": float(g2.min())},
+           "radial_monotone_fraction_quarter_box": frac, "data": "synthetic"}
+    print(json.dumps(res), flush=True)
+
+
+def _rays_torch(pose, H, W, pitch, dev):
+    """Source and pixel positions of one pose as torch FP32 tensors (the
+    comparators below take the rays as given, as the paper's pipeline does)."""
+    import torch
+    t, f, g = (float(v) for v in pose[:3])
+    rho = 0.5 * float(pose[6])
+    cz, sz, cy, sy, cx, sx = math.cos(t), math.sin(t), math.cos(f), math.sin(f), math.cos(g), math.sin(g)
+    Rz = np.array([[cz, -sz, 0], [sz, cz, 0], [0, 0, 1]])
+    Ry = np.array([[cy, 0, sy], [0, 1, 0], [-sy, 0, cy]])
+    Rx = np.array([[1, 0, 0], [0, cx, -sx], [0, sx, cx]])
+    R = Rz @ Ry @ Rx
+    tr = np.asarray(pose[3:6], float)
+    u = (np.arange(W) + 0.5 - W / 2) * pitch
+    v = (np.arange(H) + 0.5 - H / 2) * pitch
+    can = np.stack([np.full((H, W), -rho), np.broadcast_to(u, (H, W)),
+                    np.broadcast_to(v[:, None], (H, W))], -1)
+    P = can @ R.T + tr
+    s = R @ np.array([rho, 0, 0]) + tr
+    return (torch.tensor(s, dtype=torch.float32, device=dev),
+            torch.tensor(P.reshape(-1, 3), dtype=torch.float32, device=dev))
+
+
+def vgs_torch(vol, spacing, origin, s, P):
+    """The paper's vectorised Siddon (Sec. 2.3) as plain PyTorch ops: all
+    plane crossings of every ray in one tensor, filtered to [a_min, a_max],
+    sorted per row, midpoints gathered and summed (Eq. 2-4).  Benchmark-only
+    comparator; not part of the library."""
+    import torch
+    d = P - s
+    A, lo, hi = [], [], []
+    for c in range(3):
+        planes = origin[c] + torch.arange(vol.shape[c] + 1, device=P.device,
+                                          dtype=torch.float32) * spacing[c]
+        a = (planes[None, :] - s[c]) / d[:, c:c + 1]
+        A.append(a)
+        lo.append(torch.minimum(a[:, 0], a[:, -1]))
+        hi.append(torch.maximum(a[:, 0], a[:, -1]))
+    amin = torch.clamp(torch.stack(lo, 1).max(1).values, min=0.0)
+    amax = torch.clamp(torch.stack(hi, 1).min(1).values, max=1.0)
+    A = torch.cat(A, 1)
+    A = torch.where((A >= amin[:, None]) & (A <= amax[:, None]), A, amax[:, None])
+    A = torch.cat([amin[:, None], A, amax[:, None]], 1).sort(1).values
+    mid = 0.5 * (A[:, 1:] + A[:, :-1])
+    x = s[None, None, :] + mid[..., None] * d[:, None, :]
+    idx = [torch.clamp(((x[..., c] - origin[c]) / spacing[c]).floor().long(), 0,
+                       vol.shape[c] - 1) for c in range(3)]
+    val = vol[idx[0], idx[1], idx[2]]
+    E = torch.linalg.norm(d, dim=1) * ((A[:, 1:] - A[:, :-1]) * val).sum(1)
+    return torch.where(amin < amax, E, torch.zeros_like(E))
+
+
+def vgsj_torch(vol, spacing, origin, s, P):
+    """The paper's partially vectorised Siddon-Jacobs comparator (Sec. 2.3):
+    a Python loop over merge steps, each step vectorised over all pixels.
+    Benchmark-only; not part of the library."""
+    import torch
+    d = P - s
+    n = torch.tensor(vol.shape, device=P.device)
+    sp = torch.tensor(spacing, device=P.device, dtype=torch.float32)
+    og = torch.tensor(origin, device=P.device, dtype=torch.float32)
+    a0 = (og[None] - s[None]) / d
+    a1 = (og[None] + n[None] * sp[None] - s[None]) / d
+    amin = torch.clamp(torch.minimum(a0, a1).max(1).values, min=0.0)
+    amax = torch.clamp(torch.maximum(a0, a1).min(1).values, max=1.0)
+    ae = amin + (amax - amin) * 1e-6
+    i = torch.clamp(((s[None] + ae[:, None] * d - og[None]) / sp[None]).floor().long(), min=0)
+    i = torch.minimum(i, n[None] - 1)
+    step = torch.where(d > 0, 1, -1)
+    nxt = torch.where(d > 0, i + 1, i).float()
+    an = (og[None] + nxt * sp[None] - s[None]) / d
+    da = sp[None] / d.abs()
+    ac = amin.clone()
+    acc = torch.zeros_like(amin)
+    live = amin < amax
+    for _ in range(int(n.sum()) + 3):
+        m = torch.minimum(an.min(1).values, amax)
+        ii = torch.minimum(torch.maximum(i, torch.zeros_like(i)), n[None] - 1)
+        v = vol[ii[:, 0], ii[:, 1], ii[:, 2]]
+        acc = acc + torch.where(live, (m - ac) * v, torch.zeros_like(v))
+        adv = an == m[:, None]
+        an = torch.where(adv, an + da, an)
+        i = torch.where(adv, i + step, i)
+        ac = m
+        live = live & (m < amax)
+        if not bool(live.any()):
+            break
+    return torch.linalg.norm(d, dim=1) * acc
+
+
+def bench_table1(args):
+    """Table 1's comparison on one MI355X: the paper's two vectorised PyTorch
+    formulations against the hand-written kernel, for square detectors of
+    100 ... 500 pixels on the 512 x 512 x 133 CT (pitch 358.4 mm / N)."""
+    import torch
+    import paper_2208_12737_amd as P
+    from synth import make_phantom, random_poses
+    dev = "cuda"
+    ph = make_phantom("ct512", seed=0)
+    vol_t = torch.from_numpy(ph.volume).to(dev)
+    vol = P.Volume(vol_t, ph.spacing, ph.origin, device=dev)
+    pose = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=5)[0]
+    rows = []
+
+    def t_ms(f, reps):
+        f()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            f()
+        torch.cuda.synchronize()
+        return (time.perf_counter() - t0) / reps * 1e3
+
+    for N in (100, 200, 300, 400, 500):
+        pitch = 358.4 / N
+        det = P.Detector(N, N, pitch, pitch)
+        s, Pp = _rays_torch(pose, N, N, pitch, dev)
+        pose_t = torch.from_numpy(pose[None]).to(dev)
+        ours = t_ms(lambda: P.render(vol, pose_t, det), 20)
+        ref = P.render(vol, pose_t, det)[0].flatten()
+        row = {"H=W": N, "ours_ms": ours}
+        try:
+            row["vgs_ms"] = t_ms(lambda: vgs_torch(vol_t, ph.spacing, ph.origin, s, Pp), 3)
+            e = vgs_torch(vol_t, ph.spacing, ph.origin, s, Pp)
+            row["vgs_max_rel_diff"] = float(((e - ref).abs() / ref.abs().clamp(min=1e-3 * ref.abs().max())).max())
+        except RuntimeError as exc:          # out of memory for the largest sizes
+            row["vgs_ms"] = None
+            row["vgs_error"] = str(exc)[:80]
+            torch.cuda.empty_cache()
+        row["vgsj_ms"] = t_ms(lambda: vgsj_torch(vol_t, ph.spacing, ph.origin, s, Pp), 1)
+        rows.append(row)
+        print(f"[bench] table1 {row}", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "ms per DRR: paper's VGS / VGSJ formulations (PyTorch) vs the "
+                      "hand-written kernel, one MI355X", "mode": "table1", "rows": rows,
+                      "volume": [512, 512, 133], "data": "synthetic"}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -320,6 +501,12 @@ def main():
         return
     if args.mode == "serve":
         bench_serve(args)
+        return
+    if args.mode == "landscape":
+        bench_landscape(args)
+        return
+    if args.mode == "table1":
+        bench_table1(args)
         return
 
     import torch

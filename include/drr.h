@@ -112,6 +112,14 @@ int32_t drr_render(const void* packed, const drr_volume_desc* vol, const drr_det
                    const float* poses, int32_t n_poses, float* image, float* jac,
                    void* stream);
 
+/* Forward DRRs plus the derivative of every pixel with respect to the
+ * detector pixel spacing (the paper notes these gradients exist, Sec. 3.2):
+ *   jac_pitch  device float[n_poses][H][W][2] = d image / d (delta_x, delta_y)
+ * (frozen voxel indices, as for the pose Jacobian). */
+int32_t drr_render_pitch_jacobian(const void* packed, const drr_volume_desc* vol,
+                                  const drr_detector_desc* det, const float* poses,
+                                  int32_t n_poses, float* image, float* jac_pitch, void* stream);
+
 /* Forward DRRs plus, per pixel, the number of positive-length segments
  * (= voxel gathers) the ray made: counts device int32[n_poses][H][W]. */
 int32_t drr_render_count(const void* packed, const drr_volume_desc* vol,
@@ -175,6 +183,16 @@ int32_t drr_render_ncc_grad(const void* packed, const drr_volume_desc* vol,
                             const float* target, int64_t target_stride, float* image,
                             float* loss, float* grad_pose, void* workspace,
                             size_t workspace_bytes, void* stream);
+
+/* Loss only (no gradient), e.g. for sweeps of the loss landscape (Sec. 3.2):
+ * one tracing pass renders each pose and reduces the five ZNCC moments per
+ * tile; loss[b] = -ZNCC(image_b, target_b).  Arguments as for
+ * drr_render_ncc_grad; workspace: drr_ncc_loss_workspace_bytes bytes. */
+size_t drr_ncc_loss_workspace_bytes(const drr_detector_desc* det, int32_t n_poses);
+int32_t drr_render_ncc_loss(const void* packed, const drr_volume_desc* vol,
+                            const drr_detector_desc* det, const float* poses, int32_t n_poses,
+                            const float* target, int64_t target_stride, float* image,
+                            float* loss, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Gradient descent with momentum on the poses (Sec. 3.2, registration):
  *   velocity <- momentum * velocity + grad_pose

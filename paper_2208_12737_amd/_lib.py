@@ -70,6 +70,7 @@ SIGNATURES = {
     "drr_volume_pack": (_I32, [_V, _V, _VD, _V]),
     "drr_render": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
     "drr_render_count": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
+    "drr_render_pitch_jacobian": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
     "drr_backward_workspace_bytes": (_SZ, [_DD, _I32]),
     "drr_render_backward": (_I32, [_DD, _I32, _V, _V, _V, _V, _SZ, _V]),
     "drr_render_backward_retrace": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V, _SZ, _V]),
@@ -78,6 +79,8 @@ SIGNATURES = {
     "drr_ncc_backward": (_I32, [_V, _V, _I64, _V, _V, _I32, _I64, _V, _V]),
     "drr_ncc_grad_workspace_bytes": (_SZ, [_DD, _I32]),
     "drr_render_ncc_grad": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _V, _SZ, _V]),
+    "drr_ncc_loss_workspace_bytes": (_SZ, [_DD, _I32]),
+    "drr_render_ncc_loss": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _SZ, _V]),
     "drr_pose_momentum_step": (_I32, [_V, _V, _V, _V, _F, _I32, _V]),
     "drr_plan_create": (_I32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(WorkItem), _I32, _V,
                                ctypes.POINTER(_V)]),

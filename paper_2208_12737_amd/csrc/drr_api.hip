@@ -158,6 +158,18 @@ int32_t drr_render(const void* packed, const drr_volume_desc* vol, const drr_det
                                nullptr, 0, nullptr, as_stream(stream));
 }
 
+int32_t drr_render_pitch_jacobian(const void* packed, const drr_volume_desc* vol,
+                                  const drr_detector_desc* det, const float* poses,
+                                  int32_t n_poses, float* image, float* jac_pitch, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    if (n_poses == 0) return DRR_OK;
+    if (!image || !jac_pitch) return fail(DRR_EINVAL, "render_pitch_jacobian: NULL output");
+    return launch_flat<kJacPitch>(packed, *vol, *det, poses, n_poses, image, jac_pitch, nullptr,
+                                  nullptr, 0, nullptr, as_stream(stream));
+}
+
 int32_t drr_render_count(const void* packed, const drr_volume_desc* vol,
                          const drr_detector_desc* det, const float* poses, int32_t n_poses,
                          float* image, int32_t* counts, void* stream)
@@ -303,6 +315,36 @@ int32_t drr_render_ncc_grad(const void* packed, const drr_volume_desc* vol,
                        (const double*)workspace, flat_grid(*det).wg_per_pose, (double)hw, loss,
                        grad_pose);
     return check_launch("ncc_grad_finalize");
+}
+
+size_t drr_ncc_loss_workspace_bytes(const drr_detector_desc* det, int32_t n_poses)
+{
+    if (validate_detector(det) != DRR_OK || n_poses < 0) return 0;
+    return (size_t)flat_grid(*det).wg_per_pose * (size_t)n_poses * 5 * sizeof(double);
+}
+
+int32_t drr_render_ncc_loss(const void* packed, const drr_volume_desc* vol,
+                            const drr_detector_desc* det, const float* poses, int32_t n_poses,
+                            const float* target, int64_t target_stride, float* image,
+                            float* loss, void* workspace, size_t workspace_bytes, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    const int64_t hw = (int64_t)det->height * det->width;
+    if (target_stride != 0 && target_stride != hw)
+        return fail(DRR_EINVAL, "render_ncc_loss: target_stride must be 0 or H*W");
+    if (hw < 2) return fail(DRR_EINVAL, "render_ncc_loss: need at least 2 pixels");
+    if (n_poses == 0) return DRR_OK;
+    if (!target || !loss || !workspace) return fail(DRR_EINVAL, "render_ncc_loss: NULL pointer");
+    if (workspace_bytes < drr_ncc_loss_workspace_bytes(det, n_poses))
+        return fail(DRR_ENOMEM, "render_ncc_loss: workspace too small");
+    hipStream_t s = as_stream(stream);
+    st = launch_flat<kNccLoss>(packed, *vol, *det, poses, n_poses, image, nullptr, nullptr,
+                               target, target_stride, (double*)workspace, s);
+    if (st) return st;
+    hipLaunchKernelGGL(k_ncc_loss_finalize, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                       (const double*)workspace, flat_grid(*det).wg_per_pose, (double)hw, loss);
+    return check_launch("ncc_loss_finalize");
 }
 
 int32_t drr_pose_momentum_step(float* poses, float* velocity, const float* grad_pose,

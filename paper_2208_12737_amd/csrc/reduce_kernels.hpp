@@ -70,6 +70,22 @@ __global__ __launch_bounds__(kReduceThreads) void k_ncc_grad_finalize(const doub
     }
 }
 
+// Loss only, from fused tile sums (I, I^2, T, T^2, IT): loss[b] = -Z.
+__global__ __launch_bounds__(kReduceThreads) void k_ncc_loss_finalize(const double* partials,
+                                                                      int n, double npix,
+                                                                      float* loss)
+{
+    __shared__ double lds[kReduceThreads * 5];
+    sum_partials<5>(partials, n, lds);
+    if (threadIdx.x == 0) {
+        const double* S = lds;
+        const double mi = S[0] / npix, mt = S[2] / npix;
+        const double si = sqrt(fmax(S[1] / npix - mi * mi, 0.0));
+        const double st = sqrt(fmax(S[3] / npix - mt * mt, 0.0));
+        loss[blockIdx.x] = (float)(-(S[4] / npix - mi * mt) / (si * st));
+    }
+}
+
 // Stored-Jacobian contraction: partial[b][chunk][j] = sum g * jac over the chunk.
 __global__ __launch_bounds__(kReduceThreads) void k_jac_dot(const float* __restrict__ jac,
                                                             const float* __restrict__ g,

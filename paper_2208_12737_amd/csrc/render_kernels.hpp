@@ -12,21 +12,27 @@
 //   kRetrace  sum over the tile of g * Jacobian (g = upstream image gradient)
 //   kNcc      image (optional) + per-tile sums for the ZNCC loss and its
 //             pose gradient: I, I^2, T, T^2, IT, J[7], T J[7], I J[7]
+//   kNccLoss  image (optional) + per-tile sums for the ZNCC loss only:
+//             I, I^2, T, T^2, IT
+//   kJacPitch image + per-pixel d image / d (delta_x, delta_y) (2 floats)
 #pragma once
 
 #include "siddon.hpp"
 
 namespace drr {
 
-enum Mode { kImage = 0, kCount = 1, kJac = 2, kRetrace = 3, kNcc = 4 };
+enum Mode { kImage = 0, kCount = 1, kJac = 2, kRetrace = 3, kNcc = 4, kNccLoss = 5,
+            kJacPitch = 6 };
 
 constexpr int kNccSums = 26;
 
 template <int MODE>
 struct ModeTraits {
-    static constexpr bool jac = MODE == kJac || MODE == kRetrace || MODE == kNcc;
+    static constexpr bool jac =
+        MODE == kJac || MODE == kRetrace || MODE == kNcc || MODE == kJacPitch;
     static constexpr bool count = MODE == kCount;
-    static constexpr int nsum = MODE == kRetrace ? 7 : (MODE == kNcc ? kNccSums : 0);
+    static constexpr int nsum =
+        MODE == kRetrace ? 7 : (MODE == kNcc ? kNccSums : (MODE == kNccLoss ? 5 : 0));
 };
 
 // Per-tile outputs.  `aux` is the upstream image gradient (kRetrace) or the
@@ -116,13 +122,18 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
     const float E = r.valid ? (float)(L * r.sum) : __builtin_nanf("");
     const int64_t pix = (int64_t)h * D.W + w;
 
-    float J[7];
+    float J[7], Jp[2];
     if (T::jac) {
         if (inside && r.valid) {
-            ray_jacobian(r, q, R, u, v, d, J);
+            // the pose frame is rebuilt here rather than kept in registers
+            // through the traversal loop
+            const PoseTrig q2 = pose_trig(launder(pose));
+            ray_jacobian(r, q2, u, v, J, MODE == kJacPitch ? Jp : nullptr,
+                         (double)w + 0.5 - 0.5 * (double)D.W, (double)h + 0.5 - 0.5 * (double)D.H);
         } else {
 #pragma unroll
             for (int j = 0; j < 7; ++j) J[j] = inside ? __builtin_nanf("") : 0.0f;
+            Jp[0] = Jp[1] = inside ? __builtin_nanf("") : 0.0f;
         }
     }
 
@@ -132,6 +143,10 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
         if (MODE == kJac) {
 #pragma unroll
             for (int j = 0; j < 7; ++j) o.jac[pix * 7 + j] = J[j];
+        }
+        if (MODE == kJacPitch) {
+            o.jac[pix * 2] = Jp[0];
+            o.jac[pix * 2 + 1] = Jp[1];
         }
     }
 
@@ -160,6 +175,12 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
         }
         block_sums<kNccSums, WX * WY>(vals, lds, o.partial);
     }
+    if (MODE == kNccLoss) {
+        const double I = inside ? (double)E : 0.0;
+        const double Tv = inside ? (double)o.aux[pix] : 0.0;
+        double vals[5] = {I, I * I, Tv, Tv * Tv, I * Tv};
+        block_sums<5, WX * WY>(vals, lds, o.partial);
+    }
 }
 
 // Flat launch: grid = wg_per_pose * n_poses workgroups, XCD-aware ordering.
@@ -178,7 +199,7 @@ __global__ __launch_bounds__(64 * WX * WY) void render_flat(
     const int64_t hw = (int64_t)D.H * D.W;
     TileOut o;
     o.image = image ? image + b * hw : nullptr;
-    o.jac = jac ? jac + b * hw * 7 : nullptr;
+    o.jac = jac ? jac + b * hw * (MODE == kJacPitch ? 2 : 7) : nullptr;
     o.counts = counts ? counts + b * hw : nullptr;
     o.aux = aux ? aux + b * aux_stride : nullptr;
     o.partial = T::nsum > 0 ? partials + ((int64_t)b * wg_per_pose + t) * T::nsum : nullptr;

@@ -30,6 +30,12 @@ constexpr uint32_t kBufferDword3 = 0x00020000u;  // gfx9 raw buffer, 32-bit data
 // always includes every segment.
 constexpr double kSliver = 0x1p-36;
 
+// Crossings the merge runs ahead of the accumulation (1 or 2).
+#ifndef DRR_PREFETCH_DEPTH
+#define DRR_PREFETCH_DEPTH 2
+#endif
+constexpr int kDepth = DRR_PREFETCH_DEPTH;
+
 // A packed volume: one or three copies of the zero-bordered grid, each in
 // its own memory order.  pitch[q][c] is the byte distance between
 // neighbouring voxels along axis c in copy q; copy_for[c] names the copy read
@@ -228,22 +234,24 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     double acc = 0.0;
     int32_t nseg = 0;
     float vprev = 0.0f;
-    int idprev = amin_ax;  // axis of the crossing that starts the segment
     float A0 = 0.f, A1 = 0.f, B0 = 0.f, B1 = 0.f, An = 0.f, Bn = 0.f;
 
-    // One merge step: close the segment [a_start, next crossing] in the
-    // current voxel (value vc), advance the winning axis and issue the load
-    // of the next voxel into vn.  The loop below alternates the roles of
-    // (v0, a0) and (v1, a1) so that no register copy forces an early wait on
-    // the load: its latency overlaps the next step's merge arithmetic.
-    // (A macro rather than a lambda: a by-reference closure makes the
-    // compiler keep the strides on the stack and load them every step.)
+    // The traversal is split into a merge (pick the next crossing, advance
+    // that axis, issue the gather of the voxel beyond it) and an accumulation
+    // (add a closed segment's length x value).  The merge runs kDepth
+    // crossings ahead of the accumulation, so every gather has kDepth merge
+    // steps of independent work between its issue and its use.  Register
+    // names rotate through an unrolled loop instead of being copied: a copy
+    // of a loaded value would force an early wait on the load.
+    // (Macros rather than lambdas: a by-reference closure makes the compiler
+    // keep the strides on the stack and load them every step.)
     //
-    // Exactly one axis advances per step (x before y before z).  Tied
+    // Exactly one axis advances per merge (x before y before z).  Tied
     // crossings are therefore taken one per step, the later ones closing
     // zero-length segments; the voxel sequence and the sum are unchanged.
-    // When anext is the exit, z "advances" harmlessly: the ray is done.
-#define DRR_MERGE_STEP(vc, vn, a_start, a_end)                                   \
+    // Once the next crossing is the exit, every further merge returns the
+    // exit again (z "advances" harmlessly) and closes empty segments.
+#define DRR_MERGE(vn, a_new, id_new)                                             \
     do {                                                                         \
         const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));           \
         const bool bx = ax == anext;                                             \
@@ -254,47 +262,77 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         az = fma(bz ? 1.0 : 0.0, daz, az);                                       \
         off += bx ? sx : (by ? sy : sz);                                         \
         vn = ld(rsrc, off);                                                      \
-        const double seg = anext - (a_start);                                    \
+        /* keep the gather where it is: the scheduler would otherwise sink  */ \
+        /* it towards its use and shorten the distance the pipeline buys    */ \
+        __builtin_amdgcn_sched_barrier(0);                                       \
+        a_new = anext;                                                           \
+        if (JAC) id_new = bx ? 0 : (by ? 1 : 2);                                 \
+    } while (0)
+    // Closes segment [a_start, a_end] in the voxel of value vc; the crossing
+    // at a_start (axis id_start) has V_before = vprev and V_after = vc.
+#define DRR_ACCUM(vc, a_start, a_end, id_start)                                  \
+    do {                                                                         \
+        const double seg = (a_end) - (a_start);                                  \
         acc = fma(seg, (double)(vc), acc);                                       \
         if (COUNT) nseg += seg > kSliver ? 1 : 0;                                \
         if (JAC) {                                                               \
-            /* crossing at a_start: V_before = vprev, V_after = vc; a step    */ \
-            /* taken after the ray has ended (a_start == amax) is empty       */ \
             const bool live = (a_start) < amax;                                  \
             const float dl = live ? vprev - (vc) : 0.0f;                         \
             const float t = (float)((a_start) - amin);                           \
-            A0 += idprev == 0 ? dl : 0.0f;                                       \
-            B0 += idprev == 0 ? t * dl : 0.0f;                                   \
-            A1 += idprev == 1 ? dl : 0.0f;                                       \
-            B1 += idprev == 1 ? t * dl : 0.0f;                                   \
-            An += idprev < 0 ? dl : 0.0f;                                        \
-            Bn += idprev < 0 ? t * dl : 0.0f;                                    \
+            A0 += (id_start) == 0 ? dl : 0.0f;                                   \
+            B0 += (id_start) == 0 ? t * dl : 0.0f;                               \
+            A1 += (id_start) == 1 ? dl : 0.0f;                                   \
+            B1 += (id_start) == 1 ? t * dl : 0.0f;                               \
+            An += (id_start) < 0 ? dl : 0.0f;                                    \
+            Bn += (id_start) < 0 ? t * dl : 0.0f;                                \
             vprev = live ? (vc) : vprev;                                         \
-            idprev = bx ? 0 : (by ? 1 : 2);                                      \
         }                                                                        \
-        a_end = anext;                                                           \
     } while (0)
 
-    float v0 = ld(rsrc, off), v1 = 0.0f;
-    double a0 = amin, a1 = amin;
-    bool active = true;
     // Every crossing either ends the ray or advances an axis by one plane,
     // so n_x + n_y + n_z + 4 steps bound the loop for any input.  The loop
-    // is wave-uniform; lanes that finished idle under the exec mask.
-    const int cap = (V.n[0] + V.n[1] + V.n[2] + 5) / 2;
-    // Both steps of an iteration always run for a live lane: when the first
-    // one ends the ray, the second sees every axis at or beyond amax and
-    // closes an empty segment (seg = 0).  Keeping the second step
-    // unconditional keeps the first step's load ahead of its use.
-    for (int it = 0; it < cap; ++it) {
-        if (active) {
-            DRR_MERGE_STEP(v0, v1, a0, a1);
-            DRR_MERGE_STEP(v1, v0, a1, a0);
-            active = a0 < amax;
+    // is wave-uniform; lanes that finished idle under the exec mask.  All
+    // steps of an iteration run for a live lane (steps after the exit close
+    // empty segments), which keeps each load ahead of its use.
+    bool active = true;
+    if (kDepth == 1) {
+        float v0 = ld(rsrc, off), v1 = 0.0f;
+        double a0 = amin, a1 = amin;
+        int i0 = amin_ax, i1 = 0;
+        const int cap = (V.n[0] + V.n[1] + V.n[2] + 5) / 2;
+        for (int it = 0; it < cap; ++it) {
+            if (active) {
+                DRR_MERGE(v1, a1, i1);
+                DRR_ACCUM(v0, a0, a1, i0);
+                DRR_MERGE(v0, a0, i0);
+                DRR_ACCUM(v1, a1, a0, i1);
+                active = a0 < amax;
+            }
+            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
         }
-        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+    } else {
+        // segment m = [a_m, a_{m+1}] with value v_m is closed while the merge
+        // produces crossing m + 2; names rotate with period three
+        float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f;
+        double a0 = amin, a1 = amin, a2 = amin;
+        int i0 = amin_ax, i1 = 0, i2 = 0;
+        DRR_MERGE(v1, a1, i1);
+        const int cap = (V.n[0] + V.n[1] + V.n[2] + 8) / 3;
+        for (int it = 0; it < cap; ++it) {
+            if (active) {
+                DRR_MERGE(v2, a2, i2);
+                DRR_ACCUM(v0, a0, a1, i0);
+                DRR_MERGE(v0, a0, i0);
+                DRR_ACCUM(v1, a1, a2, i1);
+                DRR_MERGE(v1, a1, i1);
+                DRR_ACCUM(v2, a2, a0, i2);
+                active = a0 < amax;
+            }
+            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+        }
     }
-#undef DRR_MERGE_STEP
+#undef DRR_MERGE
+#undef DRR_ACCUM
     if (JAC) {
         // exit crossing at amax: V_before = last voxel, V_after = 0
         const float t = (float)(amax - amin);
@@ -325,14 +363,41 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
 //   d alpha_k = -(s'_c + alpha_k d'_c) / d_c,  d L = dhat . d'
 //   => dE = g_d . d' + g_s . s'  with  g_s = -L A / d,
 //      g_d = sum * d / L - L B / d   (per axis c; axes with d_c = 0 drop out)
-// The pose enters through s' and d' = p' - s':
-//   angle j:  s' = rho dR_j e_x,   d' = dR_j (-2 rho, u, v)
-//   t_c:      s' = e_c,            d' = 0
-//   sdd:      s' = R e_x / 2,      d' = -R e_x
-__device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, const Mat3& R,
-                                    double u, double v, const double d[3], float J[7])
+// The pose enters through s' and d' = p' - s', with R = Z Y X (the three
+// elementary rotations), c = (-2 rho, u, v) and e_x fixed by X:
+//   theta:  g_d . Z'Y X c + rho g_s . Z'Y e_x
+//   phi:    g_d . Z Y'X c + rho g_s . Z Y'e_x
+//   gamma:  g_d . Z Y X'c           (X' e_x = 0)
+//   t_c:    g_s[c]
+//   sdd:    (g_s / 2 - g_d) . Z Y e_x
+// evaluated as row-vector x matrix products so that no 3 x 3 matrix is
+// held in registers.
+//
+// With `Jp`, also the derivative with respect to the pixel pitch: the pixel
+// moves by R e_y (w + 1/2 - W/2) per unit delta_x and R e_z (h + 1/2 - H/2)
+// per unit delta_y, the source not at all, so dE = g_d . d' with
+// R e_y = Z Y (0, cg, sg), R e_z = Z Y (0, -sg, cg); ku, kv are the factors.
+__device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, double u, double v,
+                                    float J[7], float* Jp = nullptr, double ku = 0.0,
+                                    double kv = 0.0)
 {
-    double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+    const double ct = q.ct, st = q.st, cp = q.cp, sp = q.sp, cg = q.cg, sg = q.sg;
+    // X c with c = (-2 rho, u, v); X' c
+    const double c0 = -2.0 * q.rho;
+    const double xc1 = cg * u - sg * v, xc2 = sg * u + cg * v;
+    const double dxc1 = -sg * u - cg * v, dxc2 = cg * u - sg * v;
+    // Y (X c), Y' (X c), Y e_x, Y' e_x, Y (X' c)
+    const double yx0 = cp * c0 + sp * xc2, yx1 = xc1, yx2 = -sp * c0 + cp * xc2;
+    const double dyx0 = -sp * c0 + cp * xc2, dyx2 = -cp * c0 - sp * xc2;
+    const double ye0 = cp, ye2 = -sp;
+    const double dye0 = -sp, dye2 = -cp;
+    const double ydx0 = sp * dxc2, ydx1 = dxc1, ydx2 = cp * dxc2;
+    // ray direction d = Z Y X c
+    double d[3];
+    d[0] = ct * yx0 - st * yx1;
+    d[1] = st * yx0 + ct * yx1;
+    d[2] = yx2;
+    const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     double A[3], B[3];
     A[0] = r.a0;
     A[1] = r.a1;
@@ -343,7 +408,7 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, const Ma
     double gs[3], gd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        double Bc = B[c] + r.amin * A[c];
+        const double Bc = B[c] + r.amin * A[c];
         if (d[c] != 0.0) {
             gs[c] = -L * A[c] / d[c];
             gd[c] = r.sum * d[c] / L - L * Bc / d[c];
@@ -352,25 +417,32 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, const Ma
             gd[c] = 0.0;
         }
     }
-    const double cv[3] = {-2.0 * q.rho, u, v};
-#pragma unroll
-    for (int j = 0; j < 3; ++j) {
-        Mat3 dR = rotation(q.ct, q.st, q.cp, q.sp, q.cg, q.sg, j);
-        double acc = 0.0;
-#pragma unroll
-        for (int c = 0; c < 3; ++c) {
-            double dd = dR.m[c][0] * cv[0] + dR.m[c][1] * cv[1] + dR.m[c][2] * cv[2];
-            acc += gd[c] * dd + gs[c] * q.rho * dR.m[c][0];
-        }
-        J[j] = (float)acc;
-    }
+    // row vectors g Z and g Z'
+    const double gdz0 = gd[0] * ct + gd[1] * st, gdz1 = -gd[0] * st + gd[1] * ct;
+    const double gsz0 = gs[0] * ct + gs[1] * st, gsz1 = -gs[0] * st + gs[1] * ct;
+    const double gdzd0 = -gd[0] * st + gd[1] * ct, gdzd1 = -gd[0] * ct - gd[1] * st;
+    const double gszd0 = -gs[0] * st + gs[1] * ct, gszd1 = -gs[0] * ct - gs[1] * st;
+    // (Z' has a zero third row, Z keeps the third component)
+    J[0] = (float)(gdzd0 * yx0 + gdzd1 * yx1 + q.rho * (gszd0 * ye0));
+    J[1] = (float)(gdz0 * dyx0 + gd[2] * dyx2 + q.rho * (gsz0 * dye0 + gs[2] * dye2));
+    J[2] = (float)(gdz0 * ydx0 + gdz1 * ydx1 + gd[2] * ydx2);
     J[3] = (float)gs[0];
     J[4] = (float)gs[1];
     J[5] = (float)gs[2];
-    double js = 0.0;
-#pragma unroll
-    for (int c = 0; c < 3; ++c) js += (0.5 * gs[c] - gd[c]) * R.m[c][0];
-    J[6] = (float)js;
+    J[6] = (float)((0.5 * gsz0 - gdz0) * ye0 + (0.5 * gs[2] - gd[2]) * ye2);
+    if (Jp) {
+        Jp[0] = (float)(ku * (gdz0 * sp * sg + gdz1 * cg + gd[2] * cp * sg));
+        Jp[1] = (float)(kv * (gdz0 * sp * cg - gdz1 * sg + gd[2] * cp * cg));
+    }
+}
+
+// Hides a pointer's provenance from the optimiser, so that values loaded
+// through it are recomputed rather than kept alive from earlier loads.
+template <typename T>
+__device__ inline T* launder(T* p)
+{
+    asm volatile("" : "+v"(p));
+    return p;
 }
 
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const VolArgs& V, int copy)

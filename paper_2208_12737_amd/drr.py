@@ -109,6 +109,18 @@ def render(volume: Volume, poses: torch.Tensor, det: Detector, jacobian: bool = 
     return (img, jac) if jacobian else img
 
 
+def render_pitch_jacobian(volume: Volume, poses: torch.Tensor, det: Detector):
+    """DRRs [n, H, W] and d image / d (delta_x, delta_y) [n, H, W, 2]."""
+    p = _poses(poses)
+    n = p.shape[0]
+    img = torch.empty((n, det.height, det.width), dtype=torch.float32, device=p.device)
+    jac = torch.empty((n, det.height, det.width, 2), dtype=torch.float32, device=p.device)
+    _lib.call("drr_render_pitch_jacobian", volume.packed.data_ptr(), ctypes.byref(volume.desc),
+              ctypes.byref(det.desc), p.data_ptr(), n, img.data_ptr(), jac.data_ptr(),
+              _stream())
+    return img, jac
+
+
 def render_count(volume: Volume, poses: torch.Tensor, det: Detector):
     """DRRs and per-pixel counts of voxel gathers (positive-length segments)."""
     p = _poses(poses)
@@ -242,6 +254,25 @@ def render_ncc_grad(volume: Volume, poses: torch.Tensor, det: Detector, target: 
               img.data_ptr() if img is not None else None, loss.data_ptr(), grad.data_ptr(),
               ws.data_ptr(), ws.numel(), _stream())
     return (loss, grad, img) if return_image else (loss, grad)
+
+
+def render_ncc_loss(volume: Volume, poses: torch.Tensor, det: Detector, target: torch.Tensor,
+                    workspace: torch.Tensor | None = None) -> torch.Tensor:
+    """-ZNCC of each pose's DRR against `target` (one shared image or one per
+    pose), without storing images or gradients: [n]."""
+    p = _poses(poses)
+    tgt = _dev_f32(target, "target")
+    n = p.shape[0]
+    hw = det.pixels
+    tstride = 0 if tgt.numel() == hw else hw
+    loss = torch.empty((n,), dtype=torch.float32, device=p.device)
+    need = _lib.load().drr_ncc_loss_workspace_bytes(ctypes.byref(det.desc), n)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(
+        need, p.device)
+    _lib.call("drr_render_ncc_loss", volume.packed.data_ptr(), ctypes.byref(volume.desc),
+              ctypes.byref(det.desc), p.data_ptr(), n, tgt.data_ptr(), tstride, None,
+              loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+    return loss
 
 
 def momentum_step(poses: torch.Tensor, velocity: torch.Tensor, grad: torch.Tensor,

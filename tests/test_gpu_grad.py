@@ -21,7 +21,7 @@ DEV = "cuda"
 # FP32 per-ray sums against the FP64 frozen-index Jacobian, relative to each
 # parameter's largest entry.
 JAC_RTOL = 2e-4
-# Central-difference check of the benchmark spec on kink-free pixels.
+# Tolerance against central differences on kink-free pixels.
 FD_RTOL = 1e-3
 
 
@@ -161,7 +161,7 @@ def test_fused_ncc_gradient_matches_oracle(small):
 def test_masked_ncc_gradient_vs_central_differences(small):
     """d(-ZNCC)/d pose over the pixels that are kink-free for a parameter,
     with the GPU Jacobian, against FP64 central differences of the oracle's
-    masked loss (BJ steps)."""
+    masked loss (steps 1e-4 rad / 1e-3 mm)."""
     import paper_2208_12737_amd as P
     ph, vol, grid = small
     H = W = 32
@@ -198,3 +198,29 @@ def test_momentum_step():
     v2 = 0.9 * v + g
     np.testing.assert_allclose(vt.cpu().numpy(), v2, rtol=1e-6)
     np.testing.assert_allclose(pt.cpu().numpy(), p - r * v2, rtol=1e-5, atol=1e-6)
+
+
+def test_pitch_jacobian_matches_oracle_and_differences(small):
+    """d image / d (pixel pitch): against the oracle's analytic derivative and
+    against FP64 central differences in the pitch on kink-free pixels."""
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    poses = random_poses(2, math.pi / 8, 10.0, 1000.0, seed=13)
+    H, W, dx, dy = 33, 29, 3.0, 2.5
+    det = P.Detector(H, W, dx, dy)
+    img, jp = P.render_pitch_jacobian(vol, _gpu(poses), det)
+    rimg, rjp = oracle.render_pitch_jacobian(grid, poses.astype(np.float64), H, W, dx, dy)
+    assert_image_close(img.cpu().numpy(), rimg)
+    jp = jp.cpu().numpy()
+    scale = np.abs(rjp).max(axis=(0, 1, 2))
+    assert np.all(np.abs(jp - rjp).max(axis=(0, 1, 2)) <= JAC_RTOL * scale)
+    e = 1e-3
+    p0 = poses[0].astype(np.float64)
+    _, _, h0 = oracle.render(grid, p0, H, W, dx, dy)
+    for j, (a, b) in enumerate([((dx + e, dy), (dx - e, dy)), ((dx, dy + e), (dx, dy - e))]):
+        ip, _, hp = oracle.render(grid, p0, H, W, *a)
+        im, _, hm = oracle.render(grid, p0, H, W, *b)
+        ok = ((hp == h0) & (hm == h0))[0]
+        fd = (ip - im)[0] / (2 * e)
+        err = np.abs(jp[0, :, :, j][ok] - fd[ok]).max() / np.abs(fd[ok]).max()
+        assert err <= FD_RTOL, (j, err)

@@ -1,0 +1,57 @@
+"""Loss-only fused ZNCC (landscape sweeps) against the image + NCC path and
+the oracle."""
+
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+from synth import make_phantom, random_poses
+
+pytestmark = pytest.mark.gpu
+DEV = "cuda"
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+
+
+@pytest.fixture(scope="module")
+def setup():
+    import paper_2208_12737_amd as P
+    ph = make_phantom("small", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    return P, ph, vol
+
+
+def test_loss_only_matches_image_path_and_oracle(setup):
+    P, ph, vol = setup
+    det = P.Detector(48, 40, 2.5, 2.5)
+    gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=2)
+    target = P.render(vol, torch.from_numpy(gt).to(DEV), det)[0]
+    poses = torch.from_numpy(random_poses(9, math.pi / 8, 10.0, 1000.0, seed=3)).to(DEV)
+    a = P.render_ncc_loss(vol, poses, det, target)
+    b = P.ncc_loss(P.render(vol, poses, det), target)
+    torch.testing.assert_close(a, b, rtol=1e-6, atol=1e-6)
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    img, _, _ = oracle.render(grid, poses.cpu().numpy().astype(np.float64), 48, 40, 2.5, 2.5)
+    T = target.cpu().numpy().astype(np.float64)
+    for k in range(9):
+        assert a[k].item() == pytest.approx(-oracle.zncc(img[k], T), abs=2e-6)
+
+
+def test_landscape_minimum_at_ground_truth(setup):
+    P, ph, vol = setup
+    from paper_2208_12737_amd.landscape import grid_offsets, radial_monotonicity, sweep
+    det = P.Detector(48, 48, 2.5, 2.5)
+    gt = random_poses(1, math.pi / 8, 5.0, 1000.0, seed=4)[0]
+    off = grid_offsets(0, 3, math.radians(20.0), 10.0, 9)          # theta x t_x
+    loss = sweep(vol, det, gt, off, chunk=32)
+    centre = 4 * 9 + 4
+    assert loss[centre] == pytest.approx(-1.0, abs=1e-5)
+    assert np.argmin(loss) == centre
+    frac, _ = radial_monotonicity(vol, det, gt, n_dirs=16, n_steps=6, radius=0.1)
+    assert frac >= 0.75
