@@ -17,6 +17,7 @@ Parity status per function:
   render_jacobian            pinned (central differences of render)
   render_pitch_jacobian      pinned (central differences of render in the pitch)
   zncc / zncc_grad           pinned (closed forms, invariances, differences)
+  l2 / l2_grad               pinned (closed forms, invariances, differences)
 """
 
 from __future__ import annotations
@@ -63,6 +64,8 @@ def _load():
     lib.orc_render_pitch_jacobian.argtypes = lib.orc_render_jacobian.argtypes
     lib.orc_zncc.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
     lib.orc_zncc.restype = ctypes.c_double
+    lib.orc_l2.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
+    lib.orc_l2.restype = ctypes.c_double
     lib.orc_openmp_max_threads.restype = ctypes.c_int
     _lib = lib
     return lib
@@ -213,3 +216,18 @@ def zncc_grad(I, T):
     g = np.zeros_like(I)
     z = float(_load().orc_zncc(_ptr(I), _ptr(T), I.size, _ptr(g)))
     return z, g.reshape(shape)
+
+
+def l2(I, T):
+    """Mean squared difference (1/N) sum (I - T)^2."""
+    I, T = _d(I).ravel(), _d(T).ravel()
+    return float(_load().orc_l2(_ptr(I), _ptr(T), I.size, None))
+
+
+def l2_grad(I, T):
+    """L2(I, T) and dL2/dI (same shape as I)."""
+    shape = np.shape(I)
+    I, T = _d(I).ravel(), _d(T).ravel()
+    g = np.zeros_like(I)
+    v = float(_load().orc_l2(_ptr(I), _ptr(T), I.size, _ptr(g)))
+    return v, g.reshape(shape)

@@ -538,6 +538,18 @@ double orc_zncc(const double *I, const double *T, int64_t n, double *grad /*null
     return z;
 }
 
+/* Mean squared difference of two images of n pixels, the L2 image loss that
+ * Sec. 3.2 compares with the negative ZNCC: loss = (1/n) sum (I - T)^2, and
+ * its gradient with respect to the first image, 2 (I - T) / n. */
+double orc_l2(const double *I, const double *T, int64_t n, double *grad /*nullable*/)
+{
+    double acc = 0.0;
+    for (int64_t i = 0; i < n; ++i) acc += (I[i] - T[i]) * (I[i] - T[i]);
+    if (grad)
+        for (int64_t i = 0; i < n; ++i) grad[i] = 2.0 * (I[i] - T[i]) / (double)n;
+    return acc / (double)n;
+}
+
 int orc_openmp_max_threads(void)
 {
 #ifdef _OPENMP

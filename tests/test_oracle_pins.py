@@ -383,3 +383,38 @@ def test_zncc_gradient_vs_central_differences():
     # the gradient is orthogonal to constant shifts and to I - mean(I)
     assert abs(g.sum()) < 1e-12
     assert abs(np.dot(g, I - I.mean())) < 1e-12
+
+
+# ---------------------------------------------------------------- L2
+
+def test_l2_closed_forms():
+    rng = np.random.default_rng(13)
+    T = rng.uniform(0, 5, (9, 7))
+    assert oracle.l2(T, T) == 0.0
+    # constant images: (a - b)^2
+    assert oracle.l2(np.full(12, 3.5), np.full(12, 1.25)) == pytest.approx(2.25 ** 2, abs=1e-15)
+    # hand example: I = (1, 2, 3), T = (1, 3, 5): (0 + 1 + 4) / 3
+    assert oracle.l2([1.0, 2.0, 3.0], [1.0, 3.0, 5.0]) == pytest.approx(5.0 / 3.0, abs=1e-15)
+    I = rng.uniform(0, 5, (9, 7))
+    # symmetric, shift invariant, quadratic in a common scale
+    assert oracle.l2(I, T) == pytest.approx(oracle.l2(T, I), rel=1e-15)
+    assert oracle.l2(I + 4.0, T + 4.0) == pytest.approx(oracle.l2(I, T), rel=1e-12)
+    assert oracle.l2(3.0 * I, 3.0 * T) == pytest.approx(9.0 * oracle.l2(I, T), rel=1e-13)
+    # a mean, not a sum: tiling the pair leaves it unchanged
+    assert oracle.l2(np.tile(I, 3), np.tile(T, 3)) == pytest.approx(oracle.l2(I, T), rel=1e-13)
+
+
+def test_l2_gradient_vs_central_differences():
+    rng = np.random.default_rng(14)
+    I, T = rng.uniform(0, 5, 40), rng.uniform(0, 5, 40)
+    v, g = oracle.l2_grad(I, T)
+    e = 1e-5
+    fd = np.zeros_like(I)
+    for i in range(I.size):
+        a, b = I.copy(), I.copy()
+        a[i] += e
+        b[i] -= e
+        fd[i] = (oracle.l2(a, T) - oracle.l2(b, T)) / (2 * e)
+    np.testing.assert_allclose(g, fd, rtol=1e-7, atol=1e-10)
+    # Euler: the loss is homogeneous of degree 2 in (I - T)
+    assert np.dot(g, I - T) == pytest.approx(2.0 * v, rel=1e-12)
