@@ -347,6 +347,21 @@ def bench_landscape(args):
            "grid_tx_ty": {"argmin_at_centre": bool(np.argmin(g2) == 129 * 64 + 64),
                           "min": float(g2.min())},
            "radial_monotone_fraction_quarter_box": frac, "data": "synthetic"}
+    # the same study with the mean-squared-difference loss
+    n2 = 65536
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    l2 = sweep(vol, det, gt, off[:n2], chunk=8192, loss="l2")
+    torch.cuda.synchronize()
+    dt2 = time.perf_counter() - t0
+    h1 = sweep(vol, det, gt, grid_offsets(0, 1, math.radians(90), math.radians(90), 129), loss="l2")
+    h2 = sweep(vol, det, gt, grid_offsets(3, 4, 30.0, 30.0, 129), loss="l2")
+    frac2, _ = radial_monotonicity(vol, det, gt, n_dirs=256, n_steps=16, radius=0.25, loss="l2")
+    res["l2"] = {"poses": n2, "poses_per_s": n2 / dt2,
+                 "loss_quantiles": [float(q) for q in np.quantile(l2, [0, 0.01, 0.5, 0.99, 1])],
+                 "grid_theta_phi_argmin_at_centre": bool(np.argmin(h1) == 129 * 64 + 64),
+                 "grid_tx_ty_argmin_at_centre": bool(np.argmin(h2) == 129 * 64 + 64),
+                 "radial_monotone_fraction_quarter_box": frac2}
     print(json.dumps(res), flush=True)
 
 

@@ -30,7 +30,9 @@
  *    same inputs give bitwise the same outputs, independent of batch size,
  *    batch composition and of which other work shares the GPU.
  *  - Pose contents are not validated: a non-finite pose yields NaN pixels.  A
- *    ray that misses the volume yields 0.
+ *    ray that misses the volume yields 0.  Voxel values must be finite: the
+ *    traversal reads a few voxels past each ray's exit and weights them by
+ *    zero, so an infinite voxel can turn unrelated pixels into NaN.
  *
  * Geometry (Sec. 2.4; reading of the paper's spherical parameterisation):
  *   pose = float[7] = {theta, phi, gamma, tx, ty, tz, sdd} (radians, mm).
@@ -193,6 +195,21 @@ int32_t drr_render_ncc_loss(const void* packed, const drr_volume_desc* vol,
                             const drr_detector_desc* det, const float* poses, int32_t n_poses,
                             const float* target, int64_t target_stride, float* image,
                             float* loss, void* workspace, size_t workspace_bytes, void* stream);
+
+/* Fused L2 objective, the alternative image loss of Sec. 3.2 (the paper
+ * reports loss landscapes like those of the negative ZNCC for it): one
+ * tracing pass renders each pose and returns
+ *   loss[b]        = (1/N) sum_i (image_b[i] - target_b[i])^2,  N = H*W
+ *   grad_pose[b][j] = (2/N) sum_i (image_b[i] - target_b[i]) d image_b[i] / d pose_j
+ * without storing the image Jacobian.  grad_pose may be NULL: then only the
+ * loss is formed, in a pass that computes no Jacobian.  Other arguments as
+ * for drr_render_ncc_grad; workspace: drr_l2_workspace_bytes bytes (enough
+ * for either form).  NaN poses give NaN losses. */
+size_t drr_l2_workspace_bytes(const drr_detector_desc* det, int32_t n_poses);
+int32_t drr_render_l2(const void* packed, const drr_volume_desc* vol,
+                      const drr_detector_desc* det, const float* poses, int32_t n_poses,
+                      const float* target, int64_t target_stride, float* image, float* loss,
+                      float* grad_pose, void* workspace, size_t workspace_bytes, void* stream);
 
 /* Gradient descent with momentum on the poses (Sec. 3.2, registration):
  *   velocity <- momentum * velocity + grad_pose

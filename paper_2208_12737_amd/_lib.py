@@ -81,6 +81,8 @@ SIGNATURES = {
     "drr_render_ncc_grad": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _V, _SZ, _V]),
     "drr_ncc_loss_workspace_bytes": (_SZ, [_DD, _I32]),
     "drr_render_ncc_loss": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _SZ, _V]),
+    "drr_l2_workspace_bytes": (_SZ, [_DD, _I32]),
+    "drr_render_l2": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _V, _SZ, _V]),
     "drr_pose_momentum_step": (_I32, [_V, _V, _V, _V, _F, _I32, _V]),
     "drr_plan_create": (_I32, [ctypes.POINTER(PlanDesc), ctypes.POINTER(WorkItem), _I32, _V,
                                ctypes.POINTER(_V)]),

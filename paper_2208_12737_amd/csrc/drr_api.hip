@@ -347,6 +347,44 @@ int32_t drr_render_ncc_loss(const void* packed, const drr_volume_desc* vol,
     return check_launch("ncc_loss_finalize");
 }
 
+size_t drr_l2_workspace_bytes(const drr_detector_desc* det, int32_t n_poses)
+{
+    if (validate_detector(det) != DRR_OK || n_poses < 0) return 0;
+    return (size_t)flat_grid(*det).wg_per_pose * (size_t)n_poses * 8 * sizeof(double);
+}
+
+int32_t drr_render_l2(const void* packed, const drr_volume_desc* vol,
+                      const drr_detector_desc* det, const float* poses, int32_t n_poses,
+                      const float* target, int64_t target_stride, float* image, float* loss,
+                      float* grad_pose, void* workspace, size_t workspace_bytes, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    const int64_t hw = (int64_t)det->height * det->width;
+    if (target_stride != 0 && target_stride != hw)
+        return fail(DRR_EINVAL, "render_l2: target_stride must be 0 or H*W");
+    if (n_poses == 0) return DRR_OK;
+    if (!target || !loss || !workspace) return fail(DRR_EINVAL, "render_l2: NULL pointer");
+    if (workspace_bytes < drr_l2_workspace_bytes(det, n_poses))
+        return fail(DRR_ENOMEM, "render_l2: workspace too small");
+    hipStream_t s = as_stream(stream);
+    const int tiles = flat_grid(*det).wg_per_pose;
+    if (grad_pose) {
+        st = launch_flat<kL2>(packed, *vol, *det, poses, n_poses, image, nullptr, nullptr, target,
+                              target_stride, (double*)workspace, s);
+        if (st) return st;
+        hipLaunchKernelGGL(k_l2_finalize<8>, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                           (const double*)workspace, tiles, (double)hw, loss, grad_pose);
+    } else {
+        st = launch_flat<kL2Loss>(packed, *vol, *det, poses, n_poses, image, nullptr, nullptr,
+                                  target, target_stride, (double*)workspace, s);
+        if (st) return st;
+        hipLaunchKernelGGL(k_l2_finalize<1>, dim3(n_poses), dim3(kReduceThreads), 0, s,
+                           (const double*)workspace, tiles, (double)hw, loss, nullptr);
+    }
+    return check_launch("l2_finalize");
+}
+
 int32_t drr_pose_momentum_step(float* poses, float* velocity, const float* grad_pose,
                                const float* rate, float momentum, int32_t n_poses, void* stream)
 {

@@ -86,6 +86,21 @@ __global__ __launch_bounds__(kReduceThreads) void k_ncc_loss_finalize(const doub
     }
 }
 
+// Mean squared difference and its pose gradient from the fused tile sums
+// ((I-T)^2 and, with NS = 8, (I-T) J[7]):
+//   loss = S_0 / N,  d loss / d pose_j = 2 S_{1+j} / N.
+template <int NS>
+__global__ __launch_bounds__(kReduceThreads) void k_l2_finalize(const double* partials, int n,
+                                                                double npix, float* loss,
+                                                                float* grad_pose)
+{
+    __shared__ double lds[kReduceThreads * NS];
+    sum_partials<NS>(partials, n, lds);
+    const int j = threadIdx.x;
+    if (j == 0) loss[blockIdx.x] = (float)(lds[0] / npix);
+    if (NS == 8 && j < 7) grad_pose[blockIdx.x * 7 + j] = (float)(2.0 * lds[1 + j] / npix);
+}
+
 // Stored-Jacobian contraction: partial[b][chunk][j] = sum g * jac over the chunk.
 __global__ __launch_bounds__(kReduceThreads) void k_jac_dot(const float* __restrict__ jac,
                                                             const float* __restrict__ g,

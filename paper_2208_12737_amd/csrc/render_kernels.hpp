@@ -15,6 +15,9 @@
 //   kNccLoss  image (optional) + per-tile sums for the ZNCC loss only:
 //             I, I^2, T, T^2, IT
 //   kJacPitch image + per-pixel d image / d (delta_x, delta_y) (2 floats)
+//   kL2       image (optional) + per-tile sums for the mean squared
+//             difference and its pose gradient: (I-T)^2, (I-T) J[7]
+//   kL2Loss   image (optional) + per-tile sum of (I-T)^2
 #pragma once
 
 #include "siddon.hpp"
@@ -22,21 +25,26 @@
 namespace drr {
 
 enum Mode { kImage = 0, kCount = 1, kJac = 2, kRetrace = 3, kNcc = 4, kNccLoss = 5,
-            kJacPitch = 6 };
+            kJacPitch = 6, kL2 = 7, kL2Loss = 8 };
 
 constexpr int kNccSums = 26;
 
 template <int MODE>
 struct ModeTraits {
     static constexpr bool jac =
-        MODE == kJac || MODE == kRetrace || MODE == kNcc || MODE == kJacPitch;
+        MODE == kJac || MODE == kRetrace || MODE == kNcc || MODE == kJacPitch || MODE == kL2;
     static constexpr bool count = MODE == kCount;
     static constexpr int nsum =
-        MODE == kRetrace ? 7 : (MODE == kNcc ? kNccSums : (MODE == kNccLoss ? 5 : 0));
+        MODE == kRetrace ? 7
+        : MODE == kNcc   ? kNccSums
+        : MODE == kNccLoss ? 5
+        : MODE == kL2    ? 8
+        : MODE == kL2Loss ? 1
+                         : 0;
 };
 
 // Per-tile outputs.  `aux` is the upstream image gradient (kRetrace) or the
-// target image (kNcc) of this pose; `partial` receives the tile's sums.
+// target image (kNcc, kNccLoss, kL2, kL2Loss) of this pose; `partial` receives the tile's sums.
 struct TileOut {
     float* image;      // [H][W] of this pose, may be NULL in kRetrace/kNcc
     float* jac;        // [H][W][7]
@@ -180,6 +188,16 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
         const double Tv = inside ? (double)o.aux[pix] : 0.0;
         double vals[5] = {I, I * I, Tv, Tv * Tv, I * Tv};
         block_sums<5, WX * WY>(vals, lds, o.partial);
+    }
+    if constexpr (MODE == kL2 || MODE == kL2Loss) {
+        const double r_ = inside ? (double)E - (double)o.aux[pix] : 0.0;
+        double vals[T::nsum];
+        vals[0] = r_ * r_;
+        if constexpr (MODE == kL2) {
+#pragma unroll
+            for (int j = 0; j < 7; ++j) vals[1 + j] = inside ? r_ * (double)J[j] : 0.0;
+        }
+        block_sums<T::nsum, WX * WY>(vals, lds, o.partial);
     }
 }
 

@@ -275,6 +275,31 @@ def render_ncc_loss(volume: Volume, poses: torch.Tensor, det: Detector, target: 
     return loss
 
 
+def render_l2(volume: Volume, poses: torch.Tensor, det: Detector, target: torch.Tensor,
+              grad: bool = True, return_image: bool = False,
+              workspace: torch.Tensor | None = None):
+    """Fused mean-squared-difference objective: loss [n] = mean (I - T)^2 per
+    pose, and with ``grad`` its pose gradient [n, 7]; returns
+    (loss, grad_pose or None[, image])."""
+    p = _poses(poses)
+    tgt = _dev_f32(target, "target")
+    n = p.shape[0]
+    hw = det.pixels
+    tstride = 0 if tgt.numel() == hw else hw
+    loss = torch.empty((n,), dtype=torch.float32, device=p.device)
+    g = torch.empty((n, 7), dtype=torch.float32, device=p.device) if grad else None
+    img = torch.empty((n, det.height, det.width), dtype=torch.float32,
+                      device=p.device) if return_image else None
+    need = _lib.load().drr_l2_workspace_bytes(ctypes.byref(det.desc), n)
+    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(
+        need, p.device)
+    _lib.call("drr_render_l2", volume.packed.data_ptr(), ctypes.byref(volume.desc),
+              ctypes.byref(det.desc), p.data_ptr(), n, tgt.data_ptr(), tstride,
+              img.data_ptr() if img is not None else None, loss.data_ptr(),
+              g.data_ptr() if g is not None else None, ws.data_ptr(), ws.numel(), _stream())
+    return (loss, g, img) if return_image else (loss, g)
+
+
 def momentum_step(poses: torch.Tensor, velocity: torch.Tensor, grad: torch.Tensor,
                   rate: torch.Tensor, momentum: float) -> None:
     """In place: velocity = momentum * velocity + grad; poses -= rate * velocity."""

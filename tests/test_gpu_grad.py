@@ -158,6 +158,46 @@ def test_fused_ncc_gradient_matches_oracle(small):
     torch.testing.assert_close(p.grad, grad, rtol=1e-4, atol=1e-4 * grad.abs().max().item())
 
 
+def test_fused_l2_matches_oracle(small):
+    """Mean squared difference and its pose gradient, fused, against the
+    oracle's image, Jacobian and L2 gradient; the loss-only form gives the
+    same loss, and the gradient equals the stored-Jacobian contraction of
+    2 (I - T) / N."""
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    H, W = 36, 44
+    det = P.Detector(H, W, 3.0, 3.0)
+    gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=18)
+    moving = random_poses(4, math.pi / 8, 10.0, 1000.0, seed=19)
+    target = P.render(vol, _gpu(gt), det)
+    loss, grad, img = P.render_l2(vol, _gpu(moving), det, target[0], return_image=True)
+    T = target.cpu().numpy()[0].astype(np.float64)
+    rimg, rjac = oracle.render_jacobian(grid, moving.astype(np.float64), H, W, 3.0, 3.0,
+                                        nthreads=4)
+    assert_image_close(img.cpu().numpy(), rimg)
+    for b in range(4):
+        v, gl = oracle.l2_grad(rimg[b], T)
+        assert loss[b].item() == pytest.approx(v, rel=1e-5)
+        ref = np.einsum("hw,hwj->j", gl, rjac[b])
+        scale = np.abs(gl).sum() * np.abs(rjac[b]).max(axis=(0, 1))
+        assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (b, grad[b], ref)
+    only, none = P.render_l2(vol, _gpu(moving), det, target[0], grad=False)
+    assert none is None
+    torch.testing.assert_close(only, loss, rtol=1e-6, atol=0.0)
+    # per-pose targets give the same result as one shared target
+    per = target.expand(4, H, W).contiguous()
+    l4, g4 = P.render_l2(vol, _gpu(moving), det, per)
+    torch.testing.assert_close(l4, loss, rtol=0.0, atol=0.0)
+    torch.testing.assert_close(g4, grad, rtol=0.0, atol=0.0)
+    gimg = (2.0 / (H * W)) * (img - target[0])
+    g2 = P.render_backward_retrace(vol, _gpu(moving), det, gimg)
+    torch.testing.assert_close(g2, grad, rtol=1e-4, atol=1e-4 * grad.abs().max().item())
+    # at the target pose the loss and gradient vanish (up to FP32 image rounding)
+    l0, g0 = P.render_l2(vol, _gpu(gt), det, target[0])
+    assert l0.item() <= 1e-12 * float((target[0].double() ** 2).mean())
+    assert g0.abs().max().item() <= 1e-5 * grad.abs().max().item()
+
+
 def test_masked_ncc_gradient_vs_central_differences(small):
     """d(-ZNCC)/d pose over the pixels that are kink-free for a parameter,
     with the GPU Jacobian, against FP64 central differences of the oracle's

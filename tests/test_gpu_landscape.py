@@ -55,3 +55,21 @@ def test_landscape_minimum_at_ground_truth(setup):
     assert np.argmin(loss) == centre
     frac, _ = radial_monotonicity(vol, det, gt, n_dirs=16, n_steps=6, radius=0.1)
     assert frac >= 0.75
+
+
+def test_l2_landscape_minimum_at_ground_truth(setup):
+    P, ph, vol = setup
+    from paper_2208_12737_amd.landscape import grid_offsets, radial_monotonicity, sweep
+    det = P.Detector(40, 40, 3.0, 3.0)
+    gt = random_poses(1, math.pi / 8, 5.0, 1000.0, seed=5)[0]
+    off = grid_offsets(1, 4, math.radians(20.0), 10.0, 7)          # phi x t_y
+    loss = sweep(vol, det, gt, off, chunk=16, loss="l2")
+    centre = 3 * 7 + 3
+    assert np.argmin(loss) == centre and loss[centre] <= 1e-9 * loss.max()
+    # loss-only values equal the fused loss-and-gradient values
+    poses = torch.from_numpy(gt[None] + off).to(DEV)
+    target = P.render(vol, torch.from_numpy(gt[None]).to(DEV), det)[0]
+    full, _ = P.render_l2(vol, poses, det, target)
+    np.testing.assert_allclose(loss, full.cpu().numpy(), rtol=1e-6, atol=0)
+    frac, _ = radial_monotonicity(vol, det, gt, n_dirs=16, n_steps=6, radius=0.1, loss="l2")
+    assert frac >= 0.75
