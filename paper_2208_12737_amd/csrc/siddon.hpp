@@ -445,11 +445,18 @@ __device__ inline T* launder(T* p)
     return p;
 }
 
+// The descriptor must live in scalar registers.  Where the volume arguments
+// were read from memory (plan item tables) the compiler cannot prove them
+// wave-uniform and would wrap every gather in a loop over distinct
+// descriptors; reading the fields through readfirstlane states that they are.
 __device__ inline __amdgpu_buffer_rsrc_t make_rsrc(const VolArgs& V, int copy)
 {
-    const char* base = (const char*)V.packed + (size_t)copy * V.copy_bytes;
-    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, (int)V.copy_bytes,
-                                             (int)kBufferDword3);
+    const uint64_t addr = (uint64_t)V.packed + (uint64_t)copy * V.copy_bytes;
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)addr);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(addr >> 32));
+    const int nrec = __builtin_amdgcn_readfirstlane((int)V.copy_bytes);
+    const char* base = (const char*)(((uint64_t)hi << 32) | lo);
+    return __builtin_amdgcn_make_buffer_rsrc((void*)base, (short)0, nrec, (int)kBufferDword3);
 }
 
 // Maps the hardware workgroup id to a logical one so that the workgroups
