@@ -38,8 +38,8 @@ METRIC = ("DRRs/sec and Gvoxel-gathers/s (fwd, fwd+bwd) at 512²×133 CT, "
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=200)
+    ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--poses", type=int, default=256)
     ap.add_argument("--latency-reps", type=int, default=200)
     ap.add_argument("--no-cpu-baseline", action="store_true")
@@ -93,9 +93,10 @@ def _source_digest():
 
 
 def profiled_traffic(plan_cfg):
-    """HBM-side bytes per forward launch from the committed rocprofv3 counter
-    summary (FETCH_SIZE, WRITE_SIZE scaled by a plain copy kernel), or None
-    when the kernel sources or launch shape changed since it was taken."""
+    """The committed rocprofv3 record of the forward kernel: HBM-side bytes
+    per launch (FETCH_SIZE, WRITE_SIZE scaled by a plain copy kernel), L2 hit
+    rate and traced duration; None when the kernel sources or launch shape
+    changed since it was taken."""
     here = os.path.dirname(os.path.abspath(__file__))
     path = os.path.join(here, "profiles", "render_fwd_ct512_det256_poses256.md")
     try:
@@ -112,7 +113,7 @@ def profiled_traffic(plan_cfg):
     for k in ("strategy", "tile_code", "wg_per_cu"):
         if rec.get(k) != plan_cfg[k]:
             return None
-    return rec.get("traffic_bytes_per_launch")
+    return rec
 
 
 def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
@@ -128,10 +129,29 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
     t0 = time.perf_counter()
     oracle.render(grid, p64[1:1 + n], det_px, det_px, pitch, pitch, nthreads=nthreads)
     dt = time.perf_counter() - t0
+    # one thread, over a band of rows of one DRR (scaled to whole DRRs)
+    rows = max(1, min(det_px, int(round(det_px * 2.0 / max(first * nthreads, 1e-6)))))
+    r0 = (det_px - rows) // 2
+    t0 = time.perf_counter()
+    oracle.render(grid, p64[:1], det_px, det_px, pitch, pitch, rows=(r0, r0 + rows), nthreads=1)
+    dt1 = time.perf_counter() - t0
+    model = ""
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
     return {"value": n / dt, "unit": "DRRs/s", "cores": nthreads, "kind": "oracle",
             "sample": f"{n} whole {det_px}x{det_px} DRRs of the benchmark poses "
                       f"({n * det_px * det_px} rays), FP64 sort-based Siddon, "
-                      f"{dt:.2f} s wall on {nthreads} threads"}
+                      f"{dt:.2f} s wall on {nthreads} threads",
+            "single_thread": {"value": rows / det_px / dt1, "unit": "DRRs/s",
+                              "sample": f"rows {r0}..{r0 + rows - 1} of one DRR "
+                                        f"({rows * det_px} rays), {dt1:.2f} s on 1 thread"},
+            "cpu_model": model, "nproc": os.cpu_count()}
 
 
 def bench_register(args):
@@ -285,7 +305,7 @@ def bench_serve(args):
     run_point(warm, None)
     sat = run_point(make_requests(args.requests, seed=2), None)
     points = []
-    for frac in (0.1, 0.3, 0.5, 0.7, 0.9, 1.1):
+    for frac in (0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2):
         q = frac * sat["achieved_rps"]
         print(f"[bench] serving at {q:.0f} req/s", file=sys.stderr, flush=True)
         pt = run_point(make_requests(args.requests, seed=int(100 * frac) + 3), q)
@@ -633,6 +653,26 @@ def main():
             lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat)
 
+    # single-DRR latency with cold caches: a 512 MiB write between launches
+    # evicts the volume from the L2s and the 256 MB Infinity Cache
+    cold = []
+    if args.latency_reps > 0:
+        flush = torch.empty((512 << 20) // 4, dtype=torch.float32, device=dev)
+        for i in range(12):
+            flush.fill_(float(i))
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc),
+                   ctypes.byref(det.desc), one.data_ptr(), 1, img1.data_ptr(), None,
+                   stream.cuda_stream)
+            b.record(stream)
+            torch.cuda.synchronize()
+            if i >= 2:
+                cold.append(a.elapsed_time(b))
+        del flush
+    cold = np.array(cold)
+
     res = {"metric": METRIC, "unit": "DRRs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": float(step_ms.mean()),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -644,12 +684,17 @@ def main():
         t_fwd = times["fwd"].mean() / 1e3
         res["value"] = nb / t_fwd
         res["fwd_ms_per_batch"] = float(times["fwd"].mean())
+        res["fwd_p50_ms"] = float(np.percentile(times["fwd"], 50))
+        res["fwd_p99_ms"] = float(np.percentile(times["fwd"], 99))
         res["gvox_gathers_per_s_fwd"] = gathers_fwd / t_fwd / 1e9
         res["gathers_per_ray_fwd"] = gathers_fwd / pixels
         achieved = bytes_fwd / t_fwd / 1e9
+        prof = profiled_traffic(plan_cfg) or {}
         res["roofline"] = {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS,
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-                           "traffic": profiled_traffic(plan_cfg),
+                           "traffic": prof.get("traffic_bytes_per_launch"),
+                           "l2_hit_rate": prof.get("l2_hit_rate"),
+                           "profiled_avg_us": prof.get("avg_duration_us"),
                            "kernel": f"{plan_cfg['strategy']} plan kernel, image mode, tile "
                                      f"code {plan_cfg['tile_code']}, {plan_cfg['wg_per_cu']} WG/CU",
                            "bytes_per_launch": bytes_fwd}
@@ -662,6 +707,8 @@ def main():
         t_fb = times["fwdbwd"].mean() / 1e3
         res["fwdbwd_drrs_per_s"] = nb / t_fb
         res["fwdbwd_ms_per_batch"] = float(times["fwdbwd"].mean())
+        res["fwdbwd_p50_ms"] = float(np.percentile(times["fwdbwd"], 50))
+        res["fwdbwd_p99_ms"] = float(np.percentile(times["fwdbwd"], 99))
         res["gvox_gathers_per_s_fwdbwd"] = gathers_bwd / t_fb / 1e9
         if "value" not in res:
             res["value"] = nb / t_fb
@@ -671,6 +718,11 @@ def main():
         res["single_drr_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
                                         "p99": float(np.percentile(lat, 99)),
                                         "drrs_per_s": float(1e3 / lat.mean())}
+    if len(cold):
+        res["single_drr_cold_cache_ms"] = {"p50": float(np.percentile(cold, 50)),
+                                           "max": float(cold.max()),
+                                           "note": "device time (HIP events) after a 512 MiB "
+                                                   "write that evicts L2 and Infinity Cache"}
     res["wall_s_timed"] = wall
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

@@ -32,7 +32,13 @@ int32_t check_launch(const char* what)
 // threads).  Fewer resident workgroups per CU than the register file allows
 // keep the gather working set inside the L1/L2 caches; the limit is imposed
 // by reserving LDS per workgroup (default 4 workgroups = 4 waves per SIMD).
-constexpr int kTW = 8, kWX = 1, kWY = 4;
+#ifndef DRR_DIRECT_SHAPE
+#define DRR_DIRECT_SHAPE 8, 1, 4
+#endif
+// Tile shape of the direct launches: pixels per wave row, waves per
+// workgroup along w and along h.
+constexpr int kShape[3] = {DRR_DIRECT_SHAPE};
+constexpr int kTW = kShape[0], kWX = kShape[1], kWY = kShape[2];
 using DefaultShape = TileShape<kTW, kWX, kWY>;
 
 // -1: by layout (4 for DRR_LAYOUT_INPUT, 6 for DRR_LAYOUT_PER_AXIS, the

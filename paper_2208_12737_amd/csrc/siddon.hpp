@@ -119,15 +119,16 @@ __device__ inline void ray_of(const PoseTrig& q, const Mat3& R, double u, double
 
 // Per-ray result.  sum = E / |d|.  For the Jacobian, crossings are grouped by
 // the axis of their plane: A_c = sum of (V_before - V_after) over the c-plane
-// crossings, B_c = sum of (alpha - alpha_min)(V_before - V_after); only x and
-// y are accumulated -- z follows from sum_k (V_before - V_after) = 0 and
-// sum_k (alpha_k - alpha_min)(V_before - V_after) = E/|d| over all
-// crossings.  Ends clamped to the ray's own [0, 1] do not move with the pose
-// and are kept apart in a_none / b_none.
+// crossings, B_c = sum of (alpha - alpha_min)(V_before - V_after).  Ends
+// clamped to the ray's own [0, 1] do not move with the pose and belong to no
+// axis.  All three axes are summed explicitly: deriving one of them from
+// sum_k (V_before - V_after) = 0 would leave it with the rounding error of
+// the other two, which the tail multiplies by |d| / d_c -- millions for a
+// ray nearly parallel to that axis's planes.
 struct RayAcc {
     double sum;
     double amin;
-    float a0, a1, b0, b1, a_none, b_none;
+    float a0, a1, a2, b0, b1, b2;
     int32_t nseg;
     bool valid;  // false: non-finite geometry (result NaN)
 };
@@ -156,7 +157,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     RayAcc r;
     r.sum = 0.0;
     r.amin = 0.0;
-    r.a0 = r.a1 = r.b0 = r.b1 = r.a_none = r.b_none = 0.0f;
+    r.a0 = r.a1 = r.a2 = r.b0 = r.b1 = r.b2 = 0.0f;
     r.nseg = 0;
     r.valid = true;
 
@@ -234,7 +235,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     double acc = 0.0;
     int32_t nseg = 0;
     float vprev = 0.0f;
-    float A0 = 0.f, A1 = 0.f, B0 = 0.f, B1 = 0.f, An = 0.f, Bn = 0.f;
+    float A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B1 = 0.f, B2 = 0.f;
 
     // The traversal is split into a merge (pick the next crossing, advance
     // that axis, issue the gather of the voxel beyond it) and an accumulation
@@ -251,7 +252,9 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // zero-length segments; the voxel sequence and the sum are unchanged.
     // Once the next crossing is the exit, every further merge returns the
     // exit again (z "advances" harmlessly) and closes empty segments.
-#define DRR_MERGE(vn, a_new, id_new)                                             \
+    // For the Jacobian each crossing carries 0/1 weights (wx, wy, wz) naming
+    // the axis of its plane, so that the per-axis sums are plain FMAs.
+#define DRR_MERGE(vn, a_new, wx_new, wy_new, wz_new)                             \
     do {                                                                         \
         const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));           \
         const bool bx = ax == anext;                                             \
@@ -266,11 +269,16 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         /* it towards its use and shorten the distance the pipeline buys    */ \
         __builtin_amdgcn_sched_barrier(0);                                       \
         a_new = anext;                                                           \
-        if (JAC) id_new = bx ? 0 : (by ? 1 : 2);                                 \
+        if (JAC) {                                                               \
+            wx_new = bx ? 1.0f : 0.0f;                                           \
+            wy_new = by ? 1.0f : 0.0f;                                           \
+            wz_new = bz ? 1.0f : 0.0f;                                           \
+        }                                                                        \
     } while (0)
     // Closes segment [a_start, a_end] in the voxel of value vc; the crossing
-    // at a_start (axis id_start) has V_before = vprev and V_after = vc.
-#define DRR_ACCUM(vc, a_start, a_end, id_start)                                  \
+    // at a_start (weights wx, wy, wz) has V_before = vprev and V_after = vc.
+    // (An entry clamped to alpha = 0 has weights 0, 0, 0.)
+#define DRR_ACCUM(vc, a_start, a_end, wx, wy, wz)                                \
     do {                                                                         \
         const double seg = (a_end) - (a_start);                                  \
         acc = fma(seg, (double)(vc), acc);                                       \
@@ -278,16 +286,19 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         if (JAC) {                                                               \
             const bool live = (a_start) < amax;                                  \
             const float dl = live ? vprev - (vc) : 0.0f;                         \
-            const float t = (float)((a_start) - amin);                           \
-            A0 += (id_start) == 0 ? dl : 0.0f;                                   \
-            B0 += (id_start) == 0 ? t * dl : 0.0f;                               \
-            A1 += (id_start) == 1 ? dl : 0.0f;                                   \
-            B1 += (id_start) == 1 ? t * dl : 0.0f;                               \
-            An += (id_start) < 0 ? dl : 0.0f;                                    \
-            Bn += (id_start) < 0 ? t * dl : 0.0f;                                \
+            const float tdl = (float)((a_start) - amin) * dl;                    \
+            A0 = fmaf((wx), dl, A0);                                             \
+            B0 = fmaf((wx), tdl, B0);                                            \
+            A1 = fmaf((wy), dl, A1);                                             \
+            B1 = fmaf((wy), tdl, B1);                                            \
+            A2 = fmaf((wz), dl, A2);                                             \
+            B2 = fmaf((wz), tdl, B2);                                            \
             vprev = live ? (vc) : vprev;                                         \
         }                                                                        \
     } while (0)
+    const float wx_entry = amin_ax == 0 ? 1.0f : 0.0f;
+    const float wy_entry = amin_ax == 1 ? 1.0f : 0.0f;
+    const float wz_entry = amin_ax == 2 ? 1.0f : 0.0f;
 
     // Every crossing either ends the ray or advances an axis by one plane,
     // so n_x + n_y + n_z + 4 steps bound the loop for any input.  The loop
@@ -298,14 +309,15 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     if (kDepth == 1) {
         float v0 = ld(rsrc, off), v1 = 0.0f;
         double a0 = amin, a1 = amin;
-        int i0 = amin_ax, i1 = 0;
+        float x0 = wx_entry, y0 = wy_entry, z0 = wz_entry;
+        float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f;
         const int cap = (V.n[0] + V.n[1] + V.n[2] + 5) / 2;
         for (int it = 0; it < cap; ++it) {
             if (active) {
-                DRR_MERGE(v1, a1, i1);
-                DRR_ACCUM(v0, a0, a1, i0);
-                DRR_MERGE(v0, a0, i0);
-                DRR_ACCUM(v1, a1, a0, i1);
+                DRR_MERGE(v1, a1, x1, y1, z1);
+                DRR_ACCUM(v0, a0, a1, x0, y0, z0);
+                DRR_MERGE(v0, a0, x0, y0, z0);
+                DRR_ACCUM(v1, a1, a0, x1, y1, z1);
                 active = a0 < amax;
             }
             if (__builtin_amdgcn_ballot_w64(active) == 0) break;
@@ -315,17 +327,18 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         // produces crossing m + 2; names rotate with period three
         float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f;
         double a0 = amin, a1 = amin, a2 = amin;
-        int i0 = amin_ax, i1 = 0, i2 = 0;
-        DRR_MERGE(v1, a1, i1);
+        float x0 = wx_entry, y0 = wy_entry, z0 = wz_entry;
+        float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f, x2 = 0.0f, y2 = 0.0f, z2 = 0.0f;
+        DRR_MERGE(v1, a1, x1, y1, z1);
         const int cap = (V.n[0] + V.n[1] + V.n[2] + 8) / 3;
         for (int it = 0; it < cap; ++it) {
             if (active) {
-                DRR_MERGE(v2, a2, i2);
-                DRR_ACCUM(v0, a0, a1, i0);
-                DRR_MERGE(v0, a0, i0);
-                DRR_ACCUM(v1, a1, a2, i1);
-                DRR_MERGE(v1, a1, i1);
-                DRR_ACCUM(v2, a2, a0, i2);
+                DRR_MERGE(v2, a2, x2, y2, z2);
+                DRR_ACCUM(v0, a0, a1, x0, y0, z0);
+                DRR_MERGE(v0, a0, x0, y0, z0);
+                DRR_ACCUM(v1, a1, a2, x1, y1, z1);
+                DRR_MERGE(v1, a1, x1, y1, z1);
+                DRR_ACCUM(v2, a2, a0, x2, y2, z2);
                 active = a0 < amax;
             }
             if (__builtin_amdgcn_ballot_w64(active) == 0) break;
@@ -334,7 +347,8 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
 #undef DRR_MERGE
 #undef DRR_ACCUM
     if (JAC) {
-        // exit crossing at amax: V_before = last voxel, V_after = 0
+        // exit crossing at amax: V_before = last voxel, V_after = 0 (an exit
+        // clamped to alpha = 1 belongs to no axis)
         const float t = (float)(amax - amin);
         if (amax_ax == 0) {
             A0 += vprev;
@@ -342,19 +356,19 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         } else if (amax_ax == 1) {
             A1 += vprev;
             B1 += t * vprev;
-        } else if (amax_ax < 0) {
-            An += vprev;
-            Bn += t * vprev;
+        } else if (amax_ax == 2) {
+            A2 += vprev;
+            B2 += t * vprev;
         }
     }
     r.sum = acc;
     r.nseg = nseg;
     r.a0 = A0;
     r.a1 = A1;
+    r.a2 = A2;
     r.b0 = B0;
     r.b1 = B1;
-    r.a_none = An;
-    r.b_none = Bn;
+    r.b2 = B2;
     return r;
 }
 
@@ -401,10 +415,10 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, double u
     double A[3], B[3];
     A[0] = r.a0;
     A[1] = r.a1;
-    A[2] = -((double)r.a0 + (double)r.a1 + (double)r.a_none);
+    A[2] = r.a2;
     B[0] = r.b0;
     B[1] = r.b1;
-    B[2] = r.sum - (double)r.b0 - (double)r.b1 - (double)r.b_none;
+    B[2] = r.b2;
     double gs[3], gd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {

@@ -56,6 +56,43 @@ def test_jacobian_matches_oracle(small, seed):
     assert np.all(err <= JAC_RTOL), err
 
 
+def _near_parallel_pose(axis, H, W, pitch, rho):
+    """A pose for which one detector ray runs almost parallel to the planes of
+    `axis` (|d_axis| of order 1e-4 mm or less against |d| ~ 2 rho)."""
+    if axis == 2:      # row H/2 - 1: d_z = 2 rho sin(phi) - (pitch / 2) cos(phi)
+        return np.array([0.2, math.atan(pitch / (4 * rho)), 0.0, 1.0, -2.0, 0.5, 2 * rho],
+                        np.float32)
+    if axis == 1:      # column W/2 - 1: d_y = -2 rho sin(theta) - (pitch / 2) cos(theta)
+        return np.array([-math.atan(pitch / (4 * rho)), 0.0, 0.0, 1.0, -2.0, 0.5, 2 * rho],
+                        np.float32)
+    # column W/2 - 1 with the central ray along y: d_x = -2 rho cos(theta) + (pitch / 2) sin(theta)
+    return np.array([math.atan2(2 * rho, -pitch / 2), 0.1, 0.0, 1.0, -2.0, 0.5, 2 * rho],
+                    np.float32)
+
+
+@pytest.mark.parametrize("axis", [0, 1, 2])
+def test_jacobian_rays_parallel_to_planes(small, axis):
+    """Rays almost parallel to one family of planes: the tail divides that
+    axis's sums by d_c, so their rounding error is multiplied by |d| / d_c
+    (here ~1e7); every axis is summed explicitly to keep that error relative
+    to the axis's own terms."""
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    H = W = 64
+    pitch, rho = 2.0, 500.0
+    pose = _near_parallel_pose(axis, H, W, pitch, rho)
+    p64 = pose.astype(np.float64)
+    dmin = min(abs((lambda sp: (sp[1] - sp[0])[axis])(oracle.ray_endpoints(p64, H, W, pitch, pitch, h, w)))
+               for h in range(H) for w in range(W))
+    assert dmin < 1e-3, dmin
+    det = P.Detector(H, W, pitch, pitch)
+    img, jac = P.render(vol, _gpu(pose[None]), det, jacobian=True)
+    rimg, rjac = oracle.render_jacobian(grid, p64[None], H, W, pitch, pitch, nthreads=4)
+    assert_image_close(img.cpu().numpy(), rimg)
+    errs = column_errors(jac.cpu().numpy()[0], rjac[0])
+    assert max(errs) <= JAC_RTOL, errs
+
+
 def test_jacobian_vs_central_differences(small):
     """Per-pixel d image / d pose against FP64 central differences of the
     oracle with steps 1e-4 rad / 1e-3 mm, on kink-free pixels."""
