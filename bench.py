@@ -47,12 +47,15 @@ def parse():
                     help="approximate CPU time (thread-seconds) for the oracle sample")
     ap.add_argument("--only", choices=["fwd", "fwdbwd", "direct"], default=None,
                     help="time one phase only (for profiling runs)")
-    ap.add_argument("--mode", choices=["drr", "register", "serve", "landscape", "table1"],
+    ap.add_argument("--mode", choices=["drr", "register", "serve", "landscape", "table1",
+                                       "gather-calibration"],
                     default="drr",
                     help="drr: the headline forward / fwd+bwd batch (default); register: "
                          "32 batched registrations; serve: the request loop over four "
                          "resident volumes at a QPS sweep; landscape: loss sweeps over "
-                         "random and gridded pose offsets")
+                         "random and gridded pose offsets; table1: the paper's PyTorch "
+                         "formulations beside the kernel; gather-calibration: cost of one "
+                         "gather instruction against the cache lines it touches")
     ap.add_argument("--requests", type=int, default=2000,
                     help="requests per QPS point in --mode serve")
     ap.add_argument("--tune-cache", default=os.path.join(
@@ -521,6 +524,39 @@ def bench_table1(args):
                       "volume": [512, 512, 133], "data": "synthetic"}), flush=True)
 
 
+def bench_gather_calibration(args):
+    """Cost of one 64-lane dword gather instruction against the number of
+    distinct 128-byte lines it touches (calib/gather_lines.hip): the ceiling
+    that scattered voxel gathers can reach on this GPU."""
+    import torch
+    here = os.path.dirname(os.path.abspath(__file__))
+    lib = ctypes.CDLL(os.path.join(here, "paper_2208_12737_amd", "calib", "libgathercal.so"))
+    lib.gathercal_run.argtypes = [ctypes.c_int32] * 5 + [ctypes.POINTER(ctypes.c_float)]
+    lib.gathercal_run.restype = ctypes.c_int32
+    lib.gathercal_clock_khz.restype = ctypes.c_int32
+    torch.cuda.init()
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    clock_ghz = lib.gathercal_clock_khz() / 1e6 or 2.4
+    blocks, iters = n_cu * 8, 4096
+    rows = []
+    for window in (1, 64, 4096):
+        for k in (1, 2, 4, 8, 16, 32, 64):
+            ms = ctypes.c_float(0.0)
+            st = lib.gathercal_run(k, window, iters, blocks, 3, ctypes.byref(ms))
+            if st != 0:
+                raise RuntimeError(f"gathercal_run failed: {st}")
+            per_cu = blocks * 4 * iters / n_cu
+            rows.append({"window_lines": window, "lines_per_instr": k, "ms": ms.value,
+                         "cycles_per_instr_per_cu": ms.value * 1e-3 * clock_ghz * 1e9 / per_cu,
+                         "g_lane_loads_per_s": blocks * 4 * iters * 64 / (ms.value * 1e-3) / 1e9})
+            print(f"[bench] gather k={k} window={window}: {rows[-1]['cycles_per_instr_per_cu']:.1f} "
+                  "cycles/instr/CU", file=sys.stderr, flush=True)
+    print(json.dumps({"metric": "cycles per 64-lane dword gather instruction per CU vs distinct "
+                      "128-B lines per instruction", "mode": "gather-calibration",
+                      "clock_ghz": clock_ghz, "cus": n_cu, "waves": blocks * 4,
+                      "instr_per_wave": iters, "rows": rows}), flush=True)
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -542,6 +578,9 @@ def main():
         return
     if args.mode == "table1":
         bench_table1(args)
+        return
+    if args.mode == "gather-calibration":
+        bench_gather_calibration(args)
         return
 
     import torch

@@ -285,10 +285,9 @@ void drr_plan_destroy(drr_plan* plan);
 /* ---------------------------------------------------------------- misc */
 
 /* Resident workgroups per CU for the direct render entry points (those not
- * going through a plan); 0 = as many as registers allow; -1 (default) = by
- * volume layout (4 for DRR_LAYOUT_INPUT, 6 for DRR_LAYOUT_PER_AXIS), which
- * trades occupancy for cache locality of the voxel gathers.  Process-wide;
- * affects launches enqueued after the call. */
+ * going through a plan); 0 = as many as registers allow; -1 (default) = 4,
+ * which trades occupancy for cache locality of the voxel gathers.
+ * Process-wide; affects launches enqueued after the call. */
 int32_t drr_set_launch_occupancy(int32_t wg_per_cu);
 
 const char* drr_status_string(int32_t status);

@@ -1,4 +1,5 @@
-"""Build libdrr.so (the HIP/gfx950 C-ABI library) in-tree with hipcc.
+"""Build libdrr.so (the HIP/gfx950 C-ABI library) in-tree with hipcc, and the
+gather-rate calibration library calib/libgathercal.so used by the benchmark.
 
 Usage: python -m paper_2208_12737_amd.build [-v]
 """
@@ -13,6 +14,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 LIB = os.path.join(HERE, "libdrr.so")
+CALIB_LIB = os.path.join(HERE, "calib", "libgathercal.so")
 ARCH = "gfx950"
 
 HIPCC_FLAGS = [
@@ -32,10 +34,10 @@ def sources():
     return sorted(glob.glob(os.path.join(HERE, "csrc", "*.hip")))
 
 
-def build(verbose: bool = False) -> str:
+def _hipcc(out: str, srcs, verbose: bool) -> str:
     hipcc = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
-    tmp = LIB + ".tmp"
-    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *sources()]
+    tmp = out + ".tmp"
+    cmd = [hipcc, *HIPCC_FLAGS, "-o", tmp, *srcs]
     if verbose:
         print(" ".join(cmd), flush=True)
     res = subprocess.run(cmd, capture_output=True, text=True)
@@ -45,8 +47,13 @@ def build(verbose: bool = False) -> str:
         raise RuntimeError(f"hipcc failed ({res.returncode}):\n{err}")
     if verbose and err.strip():
         print(err)
-    os.replace(tmp, LIB)
-    return LIB
+    os.replace(tmp, out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    _hipcc(CALIB_LIB, [os.path.join(HERE, "calib", "gather_lines.hip")], verbose)
+    return _hipcc(LIB, sources(), verbose)
 
 
 if __name__ == "__main__":

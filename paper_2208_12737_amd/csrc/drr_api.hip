@@ -27,13 +27,15 @@ int32_t check_launch(const char* what)
     return DRR_OK;
 }
 
-// Launch shape of the direct (non-plan) entry points: 8 x 8-pixel wave
-// tiles, 4 waves stacked along the detector rows (8 x 32 pixels, 256
-// threads).  Fewer resident workgroups per CU than the register file allows
-// keep the gather working set inside the L1/L2 caches; the limit is imposed
-// by reserving LDS per workgroup (default 4 workgroups = 4 waves per SIMD).
+// Launch shape of the direct (non-plan) entry points: 4 x 16-pixel wave
+// tiles (4 columns, 16 rows), 4 waves side by side (16 x 16 pixels, 256
+// threads).  Of nine shapes timed on the 256-pose CT batch this one was the
+// fastest for the image mode and level with the best for the fused gradient.
+// Fewer resident workgroups per CU than the register file allows keep the
+// gather working set inside the L1/L2 caches; the limit is imposed by
+// reserving LDS per workgroup (default 4 workgroups = 4 waves per SIMD).
 #ifndef DRR_DIRECT_SHAPE
-#define DRR_DIRECT_SHAPE 8, 1, 4
+#define DRR_DIRECT_SHAPE 4, 4, 1
 #endif
 // Tile shape of the direct launches: pixels per wave row, waves per
 // workgroup along w and along h.
@@ -41,14 +43,16 @@ constexpr int kShape[3] = {DRR_DIRECT_SHAPE};
 constexpr int kTW = kShape[0], kWX = kShape[1], kWY = kShape[2];
 using DefaultShape = TileShape<kTW, kWX, kWY>;
 
-// -1: by layout (4 for DRR_LAYOUT_INPUT, 6 for DRR_LAYOUT_PER_AXIS, the
-// fastest settings measured on the 512 x 512 x 133 CT workload)
+// -1: the default, 4 resident workgroups per CU: with 4 x 16-pixel waves in
+// 16 x 16-pixel tiles it was the fastest setting for the image and the fused
+// gradient modes on the 512 x 512 x 133 CT workload (fewer resident rays keep
+// their gathers' lines in the 32 KB L1)
 static int g_wg_per_cu = -1;
 
 static int wg_per_cu_for(const drr_volume_desc& vol)
 {
-    if (g_wg_per_cu >= 0) return g_wg_per_cu;
-    return vol.layout == DRR_LAYOUT_PER_AXIS ? 6 : 4;
+    (void)vol;
+    return g_wg_per_cu >= 0 ? g_wg_per_cu : 4;
 }
 
 struct FlatGrid {

@@ -431,11 +431,12 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, double u
             gd[c] = 0.0;
         }
     }
-    // row vectors g Z and g Z'
+    // row vectors g Z and g Z' (for g_s only the first components: it meets
+    // only Y e_x and Y' e_x, whose second component is zero)
     const double gdz0 = gd[0] * ct + gd[1] * st, gdz1 = -gd[0] * st + gd[1] * ct;
-    const double gsz0 = gs[0] * ct + gs[1] * st, gsz1 = -gs[0] * st + gs[1] * ct;
+    const double gsz0 = gs[0] * ct + gs[1] * st;
     const double gdzd0 = -gd[0] * st + gd[1] * ct, gdzd1 = -gd[0] * ct - gd[1] * st;
-    const double gszd0 = -gs[0] * st + gs[1] * ct, gszd1 = -gs[0] * ct - gs[1] * st;
+    const double gszd0 = -gs[0] * st + gs[1] * ct;
     // (Z' has a zero third row, Z keeps the third component)
     J[0] = (float)(gdzd0 * yx0 + gdzd1 * yx1 + q.rho * (gszd0 * ye0));
     J[1] = (float)(gdz0 * dyx0 + gd[2] * dyx2 + q.rho * (gsz0 * dye0 + gs[2] * dye2));

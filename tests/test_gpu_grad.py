@@ -93,6 +93,33 @@ def test_jacobian_rays_parallel_to_planes(small, axis):
     assert max(errs) <= JAC_RTOL, errs
 
 
+def test_jacobian_with_clamped_ends(small):
+    """Source and detector inside the volume (SDD 40 mm in a 64 mm cube): the
+    ray ends are clamped to alpha = 0 and 1 and belong to no plane.  GPU
+    Jacobian against the oracle's, and both against FP64 central differences
+    on kink-free pixels."""
+    import paper_2208_12737_amd as P
+    ph, vol, grid = small
+    H = W = 24
+    pitch = 1.5
+    pose = np.array([0.3, 0.2, 0.1, 1.0, 2.0, 3.0, 40.0], np.float32)
+    det = P.Detector(H, W, pitch, pitch)
+    img, jac = P.render(vol, _gpu(pose[None]), det, jacobian=True)
+    p64 = pose.astype(np.float64)
+    rimg, rjac = oracle.render_jacobian(grid, p64[None], H, W, pitch, pitch)
+    assert_image_close(img.cpu().numpy(), rimg)
+    errs = column_errors(jac.cpu().numpy()[0], rjac[0])
+    assert max(errs) <= JAC_RTOL, errs
+    fd, ok = oracle.render_fd(grid, p64, H, W, pitch, pitch, [1e-4] * 3 + [1e-3] * 4)
+    J = jac.cpu().numpy()[0].astype(np.float64)
+    for j in range(7):
+        m = ok[:, :, j]
+        assert m.sum() > 50, (j, int(m.sum()))
+        scale = np.abs(J[:, :, j]).max()
+        assert np.abs(J[:, :, j][m] - fd[:, :, j][m]).max() <= FD_RTOL * scale, j
+        assert np.abs(rjac[0, :, :, j][m] - fd[:, :, j][m]).max() <= 1e-4 * scale, j
+
+
 def test_jacobian_vs_central_differences(small):
     """Per-pixel d image / d pose against FP64 central differences of the
     oracle with steps 1e-4 rad / 1e-3 mm, on kink-free pixels."""
