@@ -734,6 +734,10 @@ def main():
                            "traffic": prof.get("traffic_bytes_per_launch"),
                            "l2_hit_rate": prof.get("l2_hit_rate"),
                            "profiled_avg_us": prof.get("avg_duration_us"),
+                           "gather_floor_ms": (prof["gather_floor_us"] / 1e3
+                                               if "gather_floor_us" in prof else None),
+                           "frac_of_gather_floor": (prof["gather_floor_us"] / 1e3 / (t_fwd * 1e3)
+                                                    if "gather_floor_us" in prof else None),
                            "kernel": f"{plan_cfg['strategy']} plan kernel, image mode, tile "
                                      f"code {plan_cfg['tile_code']}, {plan_cfg['wg_per_cu']} WG/CU",
                            "bytes_per_launch": bytes_fwd}
