@@ -201,23 +201,29 @@ def test_ct512_full_image_one_pose(ct512):
 
 
 def test_layouts_render_identically(small, ct512):
-    """The per-axis copies only change memory order: renders are bitwise equal
-    to the single-copy layout, for poses whose central ray runs along x, y
-    and z."""
+    """The per-axis copies only change memory order: renders, counts and
+    Jacobians are bitwise equal to the single-copy layout, for poses whose
+    central ray runs along x, y and z (both signs), on the clinical volume,
+    the small cube and an odd-sized anisotropic grid."""
     P = _lib_objs()
-    for ph, _, _ in (small, ct512):
-        v_in = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV,
-                        layout="input")
-        v_ax = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV,
-                        layout="per_axis")
-        assert v_ax.nbytes == 3 * v_in.nbytes
-        base = random_poses(6, 0.3, 5.0, 1000.0, seed=31)
+    rng = np.random.default_rng(5)
+    odd = (rng.uniform(0, 2, (13, 7, 22)).astype(np.float32), (1.3, 0.9, 2.1),
+           (-5.0, -4.0, -20.0))
+    vols = [(ph.volume, ph.spacing, ph.origin) for ph, _, _ in (small, ct512)] + [odd]
+    for data, spacing, origin in vols:
+        v = {lay: P.Volume(torch.from_numpy(data), spacing, origin, device=DEV, layout=lay)
+             for lay in ("input", "per_axis")}
+        assert v["per_axis"].nbytes == 3 * v["input"].nbytes
+        base = random_poses(8, 0.3, 5.0, 1000.0, seed=31)
         base[2:4, 0] += math.pi / 2          # central ray along y
         base[4:6, 1] += math.pi / 2          # central ray along z
+        base[6:8, 0] += math.pi              # central ray along -x
         det = P.Detector(48, 40, 3.0, 3.0)
-        a = P.render(v_in, _gpu(base), det)
-        b = P.render(v_ax, _gpu(base), det)
-        assert torch.equal(a, b)
-        ia, ja = P.render(v_in, _gpu(base), det, jacobian=True)
-        ib, jb = P.render(v_ax, _gpu(base), det, jacobian=True)
-        assert torch.equal(ja, jb)
+        a = P.render(v["input"], _gpu(base), det)
+        ia, ja = P.render(v["input"], _gpu(base), det, jacobian=True)
+        _, ca = P.render_count(v["input"], _gpu(base), det)
+        for lay in ("per_axis",):
+            assert torch.equal(a, P.render(v[lay], _gpu(base), det)), lay
+            ib, jb = P.render(v[lay], _gpu(base), det, jacobian=True)
+            assert torch.equal(ja, jb), lay
+            assert torch.equal(ca, P.render_count(v[lay], _gpu(base), det)[1]), lay
