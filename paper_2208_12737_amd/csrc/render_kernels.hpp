@@ -124,7 +124,16 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
     r.a0 = r.a1 = r.a2 = r.b0 = r.b1 = r.b2 = 0.0f;
     r.nseg = 0;
     r.valid = true;
-    if (inside) r = trace<T::jac, T::count>(V, rsrc, pitch, s, d);
+    if (inside) {
+        if (!T::jac)
+            r = trace<false, T::count, 0>(V, rsrc, pitch, s, d);
+        else if (__builtin_amdgcn_readfirstlane(principal) == 0)
+            r = trace<T::jac, T::count, 0>(V, rsrc, pitch, s, d);
+        else if (__builtin_amdgcn_readfirstlane(principal) == 1)
+            r = trace<T::jac, T::count, 1>(V, rsrc, pitch, s, d);
+        else
+            r = trace<T::jac, T::count, 2>(V, rsrc, pitch, s, d);
+    }
 
     const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
     const float E = r.valid ? (float)(L * r.sum) : __builtin_nanf("");

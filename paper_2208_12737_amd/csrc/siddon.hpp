@@ -121,10 +121,13 @@ __device__ inline void ray_of(const PoseTrig& q, const Mat3& R, double u, double
 // the axis of their plane: A_c = sum of (V_before - V_after) over the c-plane
 // crossings, B_c = sum of (alpha - alpha_min)(V_before - V_after).  Ends
 // clamped to the ray's own [0, 1] do not move with the pose and belong to no
-// axis.  All three axes are summed explicitly: deriving one of them from
-// sum_k (V_before - V_after) = 0 would leave it with the rounding error of
-// the other two, which the tail multiplies by |d| / d_c -- millions for a
-// ray nearly parallel to that axis's planes.
+// axis.  Two axes are summed in the loop; the third follows from
+// sum_k (V_before - V_after) = 0 and sum_k (alpha_k - alpha_min)(V_before -
+// V_after) = E/|d| over all crossings.  That third axis carries the rounding
+// error of the other two, which the tail multiplies by |d| / |d_c|, so it is
+// the pose's principal axis (|d| / |d_c| <= ~2.5 for every ray of a pose);
+// deriving an axis whose planes a ray runs almost parallel to would multiply
+// the error by millions.
 struct RayAcc {
     double sum;
     double amin;
@@ -150,10 +153,16 @@ __device__ inline double min_nn(double a, double b)
     return r;
 }
 
-template <bool JAC, bool COUNT>
+// DERIVED is the axis whose Jacobian sums come from the identities rather
+// than the loop: the principal axis of the pose's central ray, so that
+// |d| / |d_DERIVED| stays small for every ray of the pose.  (A template
+// argument: with a run-time axis the compiler selects between the per-lane
+// crossing masks with several VALU instructions per step.)
+template <bool JAC, bool COUNT, int DERIVED>
 __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
                                const int32_t pitch[3], const double s[3], const double d[3])
 {
+    constexpr int derived = DERIVED;
     RayAcc r;
     r.sum = 0.0;
     r.amin = 0.0;
@@ -232,10 +241,13 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     const double dax = X0.da, day = Y0.da, daz = Z0.da;
     const uint32_t sx = X0.stride, sy = Y0.stride, sz = Z0.stride;
     uint32_t off = X0.off + Y0.off + Z0.off;
+    const uint32_t off_entry = off;
     double acc = 0.0;
     int32_t nseg = 0;
     float vprev = 0.0f;
-    float A0 = 0.f, A1 = 0.f, A2 = 0.f, B0 = 0.f, B1 = 0.f, B2 = 0.f;
+    // sums of the two explicitly accumulated axes e1 < e2 (all but `derived`)
+    constexpr int e1 = derived == 0 ? 1 : 0, e2 = derived == 2 ? 1 : 2;
+    float A1s = 0.f, A2s = 0.f, B1s = 0.f, B2s = 0.f;
 
     // The traversal is split into a merge (pick the next crossing, advance
     // that axis, issue the gather of the voxel beyond it) and an accumulation
@@ -252,9 +264,10 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // zero-length segments; the voxel sequence and the sum are unchanged.
     // Once the next crossing is the exit, every further merge returns the
     // exit again (z "advances" harmlessly) and closes empty segments.
-    // For the Jacobian each crossing carries 0/1 weights (wx, wy, wz) naming
-    // the axis of its plane, so that the per-axis sums are plain FMAs.
-#define DRR_MERGE(vn, a_new, wx_new, wy_new, wz_new)                             \
+    // For the Jacobian each crossing carries 0/1 weights (w1, w2) saying
+    // whether its plane belongs to axis e1 or e2, so that the sums are plain
+    // FMAs.
+#define DRR_MERGE(vn, a_new, w1_new, w2_new)                                     \
     do {                                                                         \
         const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));           \
         const bool bx = ax == anext;                                             \
@@ -270,15 +283,15 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         __builtin_amdgcn_sched_barrier(0);                                       \
         a_new = anext;                                                           \
         if (JAC) {                                                               \
-            wx_new = bx ? 1.0f : 0.0f;                                           \
-            wy_new = by ? 1.0f : 0.0f;                                           \
-            wz_new = bz ? 1.0f : 0.0f;                                           \
+            const bool b1 = e1 == 0 ? bx : by;                                   \
+            const bool b2 = e2 == 2 ? bz : by;                                   \
+            w1_new = b1 ? 1.0f : 0.0f;                                           \
+            w2_new = b2 ? 1.0f : 0.0f;                                           \
         }                                                                        \
     } while (0)
     // Closes segment [a_start, a_end] in the voxel of value vc; the crossing
-    // at a_start (weights wx, wy, wz) has V_before = vprev and V_after = vc.
-    // (An entry clamped to alpha = 0 has weights 0, 0, 0.)
-#define DRR_ACCUM(vc, a_start, a_end, wx, wy, wz)                                \
+    // at a_start (weights w1, w2) has V_before = vprev and V_after = vc.
+#define DRR_ACCUM(vc, a_start, a_end, w1, w2)                                    \
     do {                                                                         \
         const double seg = (a_end) - (a_start);                                  \
         acc = fma(seg, (double)(vc), acc);                                       \
@@ -287,18 +300,15 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
             const bool live = (a_start) < amax;                                  \
             const float dl = live ? vprev - (vc) : 0.0f;                         \
             const float tdl = (float)((a_start) - amin) * dl;                    \
-            A0 = fmaf((wx), dl, A0);                                             \
-            B0 = fmaf((wx), tdl, B0);                                            \
-            A1 = fmaf((wy), dl, A1);                                             \
-            B1 = fmaf((wy), tdl, B1);                                            \
-            A2 = fmaf((wz), dl, A2);                                             \
-            B2 = fmaf((wz), tdl, B2);                                            \
+            A1s = fmaf((w1), dl, A1s);                                           \
+            B1s = fmaf((w1), tdl, B1s);                                          \
+            A2s = fmaf((w2), dl, A2s);                                           \
+            B2s = fmaf((w2), tdl, B2s);                                          \
             vprev = live ? (vc) : vprev;                                         \
         }                                                                        \
     } while (0)
-    const float wx_entry = amin_ax == 0 ? 1.0f : 0.0f;
-    const float wy_entry = amin_ax == 1 ? 1.0f : 0.0f;
-    const float wz_entry = amin_ax == 2 ? 1.0f : 0.0f;
+    const float w1_entry = amin_ax == e1 ? 1.0f : 0.0f;
+    const float w2_entry = amin_ax == e2 ? 1.0f : 0.0f;
 
     // Every crossing either ends the ray or advances an axis by one plane,
     // so n_x + n_y + n_z + 4 steps bound the loop for any input.  The loop
@@ -309,15 +319,14 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     if (kDepth == 1) {
         float v0 = ld(rsrc, off), v1 = 0.0f;
         double a0 = amin, a1 = amin;
-        float x0 = wx_entry, y0 = wy_entry, z0 = wz_entry;
-        float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f;
+        float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f;
         const int cap = (V.n[0] + V.n[1] + V.n[2] + 5) / 2;
         for (int it = 0; it < cap; ++it) {
             if (active) {
-                DRR_MERGE(v1, a1, x1, y1, z1);
-                DRR_ACCUM(v0, a0, a1, x0, y0, z0);
-                DRR_MERGE(v0, a0, x0, y0, z0);
-                DRR_ACCUM(v1, a1, a0, x1, y1, z1);
+                DRR_MERGE(v1, a1, p1, q1);
+                DRR_ACCUM(v0, a0, a1, p0, q0);
+                DRR_MERGE(v0, a0, p0, q0);
+                DRR_ACCUM(v1, a1, a0, p1, q1);
                 active = a0 < amax;
             }
             if (__builtin_amdgcn_ballot_w64(active) == 0) break;
@@ -327,18 +336,17 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         // produces crossing m + 2; names rotate with period three
         float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f;
         double a0 = amin, a1 = amin, a2 = amin;
-        float x0 = wx_entry, y0 = wy_entry, z0 = wz_entry;
-        float x1 = 0.0f, y1 = 0.0f, z1 = 0.0f, x2 = 0.0f, y2 = 0.0f, z2 = 0.0f;
-        DRR_MERGE(v1, a1, x1, y1, z1);
+        float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f, p2 = 0.0f, q2 = 0.0f;
+        DRR_MERGE(v1, a1, p1, q1);
         const int cap = (V.n[0] + V.n[1] + V.n[2] + 8) / 3;
         for (int it = 0; it < cap; ++it) {
             if (active) {
-                DRR_MERGE(v2, a2, x2, y2, z2);
-                DRR_ACCUM(v0, a0, a1, x0, y0, z0);
-                DRR_MERGE(v0, a0, x0, y0, z0);
-                DRR_ACCUM(v1, a1, a2, x1, y1, z1);
-                DRR_MERGE(v1, a1, x1, y1, z1);
-                DRR_ACCUM(v2, a2, a0, x2, y2, z2);
+                DRR_MERGE(v2, a2, p2, q2);
+                DRR_ACCUM(v0, a0, a1, p0, q0);
+                DRR_MERGE(v0, a0, p0, q0);
+                DRR_ACCUM(v1, a1, a2, p1, q1);
+                DRR_MERGE(v1, a1, p1, q1);
+                DRR_ACCUM(v2, a2, a0, p2, q2);
                 active = a0 < amax;
             }
             if (__builtin_amdgcn_ballot_w64(active) == 0) break;
@@ -346,29 +354,37 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     }
 #undef DRR_MERGE
 #undef DRR_ACCUM
-    if (JAC) {
-        // exit crossing at amax: V_before = last voxel, V_after = 0 (an exit
-        // clamped to alpha = 1 belongs to no axis)
-        const float t = (float)(amax - amin);
-        if (amax_ax == 0) {
-            A0 += vprev;
-            B0 += t * vprev;
-        } else if (amax_ax == 1) {
-            A1 += vprev;
-            B1 += t * vprev;
-        } else if (amax_ax == 2) {
-            A2 += vprev;
-            B2 += t * vprev;
-        }
-    }
     r.sum = acc;
     r.nseg = nseg;
-    r.a0 = A0;
-    r.a1 = A1;
-    r.a2 = A2;
-    r.b0 = B0;
-    r.b1 = B1;
-    r.b2 = B2;
+    if (JAC) {
+        // Ends clamped to alpha = 0 or 1 belong to no axis (sums Ac, Bc); the
+        // derived axis takes what the identities leave:
+        //   A_d = -(A_e1 + A_e2 + Ac),  B_d = E/|d| - B_e1 - B_e2 - Bc.
+        float Ac = 0.0f, Bc = 0.0f;
+        // entry clamped to alpha = 0 (source inside the grid): V_before = 0,
+        // V_after = the first voxel, alpha - alpha_min = 0
+        if (amin_ax < 0) Ac -= ld(rsrc, off_entry);
+        // exit crossing at amax: V_before = last voxel, V_after = 0
+        const float t = (float)(amax - amin);
+        if (amax_ax == e1) {
+            A1s += vprev;
+            B1s += t * vprev;
+        } else if (amax_ax == e2) {
+            A2s += vprev;
+            B2s += t * vprev;
+        } else if (amax_ax < 0) {
+            Ac += vprev;
+            Bc += t * vprev;
+        }
+        const float Ad = -(A1s + A2s + Ac);
+        const float Bd = (float)(acc - (double)B1s - (double)B2s - (double)Bc);
+        r.a0 = derived == 0 ? Ad : A1s;
+        r.b0 = derived == 0 ? Bd : B1s;
+        r.a1 = derived == 0 ? A1s : (derived == 1 ? Ad : A2s);
+        r.b1 = derived == 0 ? B1s : (derived == 1 ? Bd : B2s);
+        r.a2 = derived == 2 ? Ad : A2s;
+        r.b2 = derived == 2 ? Bd : B2s;
+    }
     return r;
 }
 
