@@ -120,7 +120,6 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
 
     RayAcc r;
     r.sum = 0.0;
-    r.amin = 0.0;
     r.a0 = r.a1 = r.a2 = r.b0 = r.b1 = r.b2 = 0.0f;
     r.nseg = 0;
     r.valid = true;

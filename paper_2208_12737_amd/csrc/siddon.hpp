@@ -119,18 +119,16 @@ __device__ inline void ray_of(const PoseTrig& q, const Mat3& R, double u, double
 
 // Per-ray result.  sum = E / |d|.  For the Jacobian, crossings are grouped by
 // the axis of their plane: A_c = sum of (V_before - V_after) over the c-plane
-// crossings, B_c = sum of (alpha - alpha_min)(V_before - V_after).  Ends
-// clamped to the ray's own [0, 1] do not move with the pose and belong to no
-// axis.  Two axes are summed in the loop; the third follows from
-// sum_k (V_before - V_after) = 0 and sum_k (alpha_k - alpha_min)(V_before -
-// V_after) = E/|d| over all crossings.  That third axis carries the rounding
+// crossings, B_c = sum of alpha (V_before - V_after).  Ends clamped to the
+// ray's own [0, 1] do not move with the pose and belong to no axis.  Two axes
+// are summed in the loop; the third follows from sum_k (V_before - V_after)
+// = 0 and sum_k alpha_k (V_before - V_after) = E/|d| over all crossings.  That third axis carries the rounding
 // error of the other two, which the tail multiplies by |d| / |d_c|, so it is
 // the pose's principal axis (|d| / |d_c| <= ~2.5 for every ray of a pose);
 // deriving an axis whose planes a ray runs almost parallel to would multiply
 // the error by millions.
 struct RayAcc {
     double sum;
-    double amin;
     float a0, a1, a2, b0, b1, b2;
     int32_t nseg;
     bool valid;  // false: non-finite geometry (result NaN)
@@ -165,7 +163,6 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     constexpr int derived = DERIVED;
     RayAcc r;
     r.sum = 0.0;
-    r.amin = 0.0;
     r.a0 = r.a1 = r.a2 = r.b0 = r.b1 = r.b2 = 0.0f;
     r.nseg = 0;
     r.valid = true;
@@ -204,7 +201,6 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
             miss = true;
         }
     }
-    r.amin = amin;
     if (miss || !(amin < amax)) return r;
 
     // Voxel just past the entry, and each axis's first crossing after it.
@@ -299,7 +295,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         if (JAC) {                                                               \
             const bool live = (a_start) < amax;                                  \
             const float dl = live ? vprev - (vc) : 0.0f;                         \
-            const float tdl = (float)((a_start) - amin) * dl;                    \
+            const float tdl = (float)(a_start) * dl;                             \
             A1s = fmaf((w1), dl, A1s);                                           \
             B1s = fmaf((w1), tdl, B1s);                                          \
             A2s = fmaf((w2), dl, A2s);                                           \
@@ -362,10 +358,10 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         //   A_d = -(A_e1 + A_e2 + Ac),  B_d = E/|d| - B_e1 - B_e2 - Bc.
         float Ac = 0.0f, Bc = 0.0f;
         // entry clamped to alpha = 0 (source inside the grid): V_before = 0,
-        // V_after = the first voxel, alpha - alpha_min = 0
+        // V_after = the first voxel, alpha = 0
         if (amin_ax < 0) Ac -= ld(rsrc, off_entry);
         // exit crossing at amax: V_before = last voxel, V_after = 0
-        const float t = (float)(amax - amin);
+        const float t = (float)amax;
         if (amax_ax == e1) {
             A1s += vprev;
             B1s += t * vprev;
@@ -438,7 +434,7 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, double u
     double gs[3], gd[3];
 #pragma unroll
     for (int c = 0; c < 3; ++c) {
-        const double Bc = B[c] + r.amin * A[c];
+        const double Bc = B[c];
         if (d[c] != 0.0) {
             gs[c] = -L * A[c] / d[c];
             gd[c] = r.sum * d[c] / L - L * Bc / d[c];
