@@ -136,22 +136,33 @@ inline DetArgs det_args(const drr_detector_desc& d)
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
 // Dynamic LDS to reserve per workgroup so that at most `wg_per_cu`
-// workgroups are resident on a CU (0 = no limit).
-inline size_t occupancy_lds(int wg_per_cu)
+// workgroups are resident on a CU (0 = no limit), for a kernel that already
+// uses `static_bytes` of LDS.  The request never exceeds what one workgroup
+// may allocate: a larger one is rejected when the dispatch starts and
+// aborts the queue.
+inline size_t occupancy_lds(int wg_per_cu, size_t static_bytes)
 {
-    static int lds_per_cu = -1;
+    static int lds_per_cu = -1, lds_per_block = -1;
     if (lds_per_cu < 0) {
-        int dev = 0, v = 0;
+        int dev = 0, v = 0, b = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
                 hipSuccess || v <= 0)
             v = 160 * 1024;
+        if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
+                hipSuccess || b <= 0)
+            b = 64 * 1024;
         lds_per_cu = v;
+        lds_per_block = b < v ? b : v;
     }
     if (wg_per_cu <= 0) return 0;
-    // a little below the share so that the kernel's static LDS still fits
-    size_t share = (size_t)lds_per_cu / (size_t)wg_per_cu;
-    return share > 1024 ? share - 1024 : 0;
+    // the workgroup's whole allocation (static + dynamic) is its share of
+    // the CU, less a margin for allocation granularity
+    const size_t share = (size_t)lds_per_cu / (size_t)wg_per_cu;
+    const size_t used = static_bytes + 512;
+    size_t dyn = share > used ? share - used : 0;
+    const size_t cap = (size_t)lds_per_block > used ? (size_t)lds_per_block - used : 0;
+    return dyn < cap ? dyn : cap;
 }
 
 }  // namespace drr

@@ -68,6 +68,14 @@ static FlatGrid flat_grid(const drr_detector_desc& d)
     return g;
 }
 
+// Static LDS of render_flat<kTW, kWX, kWY, MODE> (its block-sum buffer).
+template <int MODE>
+static constexpr size_t flat_static_lds()
+{
+    return sizeof(double) * (size_t)(ModeTraits<MODE>::nsum > 0 ? ModeTraits<MODE>::nsum : 1) *
+           (size_t)(kWX * kWY);
+}
+
 template <int MODE>
 static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
                            const drr_detector_desc& det, const float* poses, int32_t n_poses,
@@ -78,7 +86,8 @@ static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
     const uint64_t blocks = (uint64_t)g.wg_per_pose * (uint64_t)n_poses;
     if (blocks > 0x7FFFFFFFull) return fail(DRR_ENOTSUP, "too many tiles in one launch");
     hipLaunchKernelGGL((render_flat<kTW, kWX, kWY, MODE>), dim3((unsigned)blocks),
-                       dim3(DefaultShape::threads), occupancy_lds(wg_per_cu_for(vol)), stream,
+                       dim3(DefaultShape::threads),
+                       occupancy_lds(wg_per_cu_for(vol), flat_static_lds<MODE>()), stream,
                        vol_args(packed, vol),
                        det_args(det), poses, g.tiles_x, g.wg_per_pose, image, jac, counts, aux,
                        aux_stride, partials);

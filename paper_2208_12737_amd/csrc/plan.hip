@@ -317,7 +317,8 @@ static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
     const int threads = 64 * sh.wx * sh.wy;
     int32_t rc;
     if (p->strategy == kFlat) {
-        const size_t lds = occupancy_lds(p->wg_per_cu);
+        // the plan kernels' own LDS: a tile index and one double
+        const size_t lds = occupancy_lds(p->wg_per_cu, 16);
         for (int m = 0; m < kPlanModes; ++m) {
             if (!(mask & (1 << m))) continue;
             hipLaunchKernelGGL(flat_kernel_for(m, p->tile_code), dim3(s.h_header->tiles[m]),
