@@ -262,6 +262,30 @@ def test_fused_l2_matches_oracle(small):
     assert g0.abs().max().item() <= 1e-5 * grad.abs().max().item()
 
 
+def test_occupancy_settings_give_identical_results(small):
+    """Every residency setting of the direct launches (1, 2, 8 workgroups per
+    CU, unlimited, default) yields bitwise the same image and fused gradient;
+    the LDS reserved to cap residency stays within the per-workgroup limit."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd import _lib
+    ph, vol, grid = small
+    det = P.Detector(40, 36, 3.0, 3.0)
+    gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=21)
+    moving = _gpu(random_poses(5, math.pi / 8, 10.0, 1000.0, seed=22))
+    target = P.render(vol, _gpu(gt), det)[0]
+    img0 = P.render(vol, moving, det)
+    loss0, grad0 = P.render_ncc_grad(vol, moving, det, target)
+    try:
+        for occ in (1, 2, 8, 0, -1):
+            _lib.call("drr_set_launch_occupancy", occ)
+            assert torch.equal(P.render(vol, moving, det), img0), occ
+            loss, grad = P.render_ncc_grad(vol, moving, det, target)
+            torch.cuda.synchronize()
+            assert torch.equal(loss, loss0) and torch.equal(grad, grad0), occ
+    finally:
+        _lib.call("drr_set_launch_occupancy", -1)
+
+
 def test_masked_ncc_gradient_vs_central_differences(small):
     """d(-ZNCC)/d pose over the pixels that are kink-free for a parameter,
     with the GPU Jacobian, against FP64 central differences of the oracle's
