@@ -138,6 +138,11 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
     t0 = time.perf_counter()
     oracle.render(grid, p64[:1], det_px, det_px, pitch, pitch, rows=(r0, r0 + rows), nthreads=1)
     dt1 = time.perf_counter() - t0
+    # the differentiable-render workload: 200 x 200 detector, image + pose
+    # Jacobian, two poses on all threads
+    t0 = time.perf_counter()
+    oracle.render_jacobian(grid, p64[:2], 200, 200, pitch, pitch, nthreads=nthreads)
+    dt_j = time.perf_counter() - t0
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -154,6 +159,9 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
             "single_thread": {"value": rows / det_px / dt1, "unit": "DRRs/s",
                               "sample": f"rows {r0}..{r0 + rows - 1} of one DRR "
                                         f"({rows * det_px} rays), {dt1:.2f} s on 1 thread"},
+            "fwd_jacobian_200x200": {"value": 2 / dt_j, "unit": "DRRs/s",
+                                     "sample": f"2 DRRs of 200x200 with d image / d pose, "
+                                               f"{dt_j:.2f} s on {nthreads} threads"},
             "cpu_model": model, "nproc": os.cpu_count()}
 
 

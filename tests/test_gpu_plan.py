@@ -134,3 +134,53 @@ def test_plan_rejects_bad_items(vols):
     with pytest.raises(_lib.DrrError):
         plan.execute([Item(5, det, ok.pose, ok.image)])   # bad volume index
     plan.close()
+
+
+def test_ct512_plan_in_the_benchmark_configuration(tmp_path):
+    """The 256-pose clinical batch (512 x 512 x 133 CT, 256 x 256 detector at
+    1.4 mm, SDD 1020 mm) through the plan with the shipped launch choice,
+    exactly as the benchmark times it: every image equals the direct render
+    bitwise, and sampled pixels match the FP64 oracle."""
+    import shutil
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Item, Plan
+    from tests._parity import image_errors
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    det = P.Detector(256, 256, 1.4, 1.4)
+    poses_np = random_poses(256, math.pi / 6, 30.0, 1020.0, seed=1)
+    poses = torch.from_numpy(poses_np).to(DEV)
+    img = torch.empty((256, 256, 256), dtype=torch.float32, device=DEV)
+    items = [Item(0, det, poses[b], img[b]) for b in range(256)]
+    shipped = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))),
+                           "paper_2208_12737_amd", "tuning.txt")
+    cache = str(tmp_path / "tuning.txt")
+    shutil.copy(shipped, cache)
+    plan = Plan([vol], max_items=256, use_graph=True, autotune=True, tune_items=items,
+                cache_path=cache)
+    with open(shipped) as fh:
+        want = fh.read().split()[1:4]
+    cfg = plan.config
+    # the shipped cache line applies to this workload: no re-tuning happened
+    assert open(cache).read() == open(shipped).read()
+    assert [str(cfg[k]) for k in ("tile_code", "wg_per_cu")] == want[1:3]
+    assert (cfg["strategy"] == "persistent") == (want[0] == "0")
+    plan.execute(items)
+    plan.execute(items)                 # graph replay
+    torch.cuda.synchronize()
+    direct = P.render(vol, poses, det)
+    assert torch.equal(img, direct)
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    rng = np.random.default_rng(3)
+    src, dst, got = [], [], []
+    for b in rng.choice(256, 8, replace=False):
+        for _ in range(30):
+            h, w = int(rng.integers(0, 256)), int(rng.integers(0, 256))
+            s, p = oracle.ray_endpoints(poses_np[b].astype(np.float64), 256, 256, 1.4, 1.4, h, w)
+            src.append(s)
+            dst.append(p)
+            got.append(float(img[b, h, w]))
+    ref, _, _ = oracle.trace_rays(grid, np.array(src), np.array(dst), nthreads=4)
+    rel, small = image_errors(np.array(got), ref)
+    assert rel <= 1e-5 and small <= 1e-5, (rel, small)
+    plan.close()
