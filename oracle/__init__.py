@@ -15,7 +15,9 @@ Parity status per function:
   trace_rays_grad            pinned (central differences of trace_rays)
   ray_endpoint_derivs        pinned (central differences of ray_endpoints)
   render_jacobian            pinned (central differences of render)
-  render_pitch_jacobian      pinned (central differences of render in the pitch)
+  render_detector_jacobian   pinned (central differences of render in the pitch and
+                             the principal-point offsets; offset = whole pixels shifts
+                             the image)
   zncc / zncc_grad           pinned (closed forms, invariances, differences)
   l2 / l2_grad               pinned (closed forms, invariances, differences)
 """
@@ -49,19 +51,22 @@ def _load():
     lib = ctypes.CDLL(_LIB_PATH)
     lib.orc_rotation.argtypes = [ctypes.c_double] * 3 + [ctypes.c_int, _dp]
     lib.orc_ray_endpoints.argtypes = [_dp, ctypes.c_int, ctypes.c_int, ctypes.c_double,
-                                      ctypes.c_double, ctypes.c_int, ctypes.c_int, _dp, _dp]
+                                      ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                      ctypes.c_int, ctypes.c_int, _dp, _dp]
     lib.orc_ray_endpoint_derivs.argtypes = lib.orc_ray_endpoints.argtypes
     lib.orc_trace_rays.argtypes = [_dp, _ip, _dp, _dp, _dp, _dp, ctypes.c_int64, _dp, _lp,
                                    _up, ctypes.c_int]
     lib.orc_render.argtypes = [_dp, _ip, _dp, _dp, _dp, ctypes.c_int32, ctypes.c_int32,
                                ctypes.c_int32, ctypes.c_double, ctypes.c_double,
+                               ctypes.c_double, ctypes.c_double,
                                ctypes.c_int32, ctypes.c_int32, _dp, _lp, _up, ctypes.c_int]
     lib.orc_trace_rays_grad.argtypes = [_dp, _ip, _dp, _dp, _dp, _dp, ctypes.c_int64, _dp,
                                         _dp, _dp, ctypes.c_int]
     lib.orc_render_jacobian.argtypes = [_dp, _ip, _dp, _dp, _dp, ctypes.c_int32,
                                         ctypes.c_int32, ctypes.c_int32, ctypes.c_double,
-                                        ctypes.c_double, _dp, _dp, ctypes.c_int]
-    lib.orc_render_pitch_jacobian.argtypes = lib.orc_render_jacobian.argtypes
+                                        ctypes.c_double, ctypes.c_double, ctypes.c_double,
+                                        _dp, _dp, ctypes.c_int]
+    lib.orc_render_detector_jacobian.argtypes = lib.orc_render_jacobian.argtypes
     lib.orc_zncc.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
     lib.orc_zncc.restype = ctypes.c_double
     lib.orc_l2.argtypes = [_dp, _dp, ctypes.c_int64, _dp]
@@ -105,16 +110,17 @@ def rotation(theta, phi, gamma, which=-1):
     return out.reshape(3, 3)
 
 
-def ray_endpoints(pose, H, W, delta_x, delta_y, h, w):
+def ray_endpoints(pose, H, W, delta_x, delta_y, h, w, offset=(0.0, 0.0)):
     s, p = np.zeros(3), np.zeros(3)
-    _load().orc_ray_endpoints(_ptr(_d(pose)), H, W, delta_x, delta_y, h, w, _ptr(s), _ptr(p))
+    _load().orc_ray_endpoints(_ptr(_d(pose)), H, W, delta_x, delta_y, offset[0], offset[1], h, w,
+                              _ptr(s), _ptr(p))
     return s, p
 
 
-def ray_endpoint_derivs(pose, H, W, delta_x, delta_y, h, w):
+def ray_endpoint_derivs(pose, H, W, delta_x, delta_y, h, w, offset=(0.0, 0.0)):
     ds, dp = np.zeros(21), np.zeros(21)
-    _load().orc_ray_endpoint_derivs(_ptr(_d(pose)), H, W, delta_x, delta_y, h, w, _ptr(ds),
-                                    _ptr(dp))
+    _load().orc_ray_endpoint_derivs(_ptr(_d(pose)), H, W, delta_x, delta_y, offset[0],
+                                    offset[1], h, w, _ptr(ds), _ptr(dp))
     return ds.reshape(3, 7), dp.reshape(3, 7)
 
 
@@ -140,10 +146,12 @@ def trace_rays_grad(grid: Grid, src, dst, nthreads=1):
     return E, gs, gp
 
 
-def render(grid: Grid, poses, H, W, delta_x, delta_y, rows=None, nthreads=1):
+def render(grid: Grid, poses, H, W, delta_x, delta_y, rows=None, nthreads=1,
+           offset=(0.0, 0.0)):
     """DRR images [B, H, W] (float64) with segment counts and sequence hashes.
 
-    ``rows = (r0, r1)`` evaluates only detector rows r0..r1-1 (others stay 0).
+    ``rows = (r0, r1)`` evaluates only detector rows r0..r1-1 (others stay 0);
+    ``offset`` is the detector's principal point (offset_u, offset_v) in mm.
     """
     poses = _d(poses).reshape(-1, 7)
     B = poses.shape[0]
@@ -151,34 +159,38 @@ def render(grid: Grid, poses, H, W, delta_x, delta_y, rows=None, nthreads=1):
     img = np.zeros((B, H, W))
     cnt = np.zeros((B, H, W), dtype=np.int64)
     hsh = np.zeros((B, H, W), dtype=np.uint64)
-    _load().orc_render(*grid.args(), _ptr(poses), B, H, W, delta_x, delta_y, r0, r1,
-                       _ptr(img), _ptr(cnt, _lp), _ptr(hsh, _up), nthreads)
+    _load().orc_render(*grid.args(), _ptr(poses), B, H, W, delta_x, delta_y, offset[0],
+                       offset[1], r0, r1, _ptr(img), _ptr(cnt, _lp), _ptr(hsh, _up), nthreads)
     return img, cnt, hsh
 
 
-def render_jacobian(grid: Grid, poses, H, W, delta_x, delta_y, nthreads=1):
+def render_jacobian(grid: Grid, poses, H, W, delta_x, delta_y, nthreads=1,
+                    offset=(0.0, 0.0)):
     """Images [B, H, W] and frozen-index Jacobians [B, H, W, 7] (float64)."""
     poses = _d(poses).reshape(-1, 7)
     B = poses.shape[0]
     img = np.zeros((B, H, W))
     jac = np.zeros((B, H, W, 7))
     _load().orc_render_jacobian(*grid.args(), _ptr(poses), B, H, W, delta_x, delta_y,
-                                _ptr(img), _ptr(jac), nthreads)
+                                offset[0], offset[1], _ptr(img), _ptr(jac), nthreads)
     return img, jac
 
 
-def render_pitch_jacobian(grid: Grid, poses, H, W, delta_x, delta_y, nthreads=1):
-    """Images [B, H, W] and d image / d (delta_x, delta_y) [B, H, W, 2]."""
+def render_detector_jacobian(grid: Grid, poses, H, W, delta_x, delta_y, nthreads=1,
+                             offset=(0.0, 0.0)):
+    """Images [B, H, W] and d image / d (delta_x, delta_y, offset_u, offset_v)
+    [B, H, W, 4]."""
     poses = _d(poses).reshape(-1, 7)
     B = poses.shape[0]
     img = np.zeros((B, H, W))
-    jac = np.zeros((B, H, W, 2))
-    _load().orc_render_pitch_jacobian(*grid.args(), _ptr(poses), B, H, W, delta_x, delta_y,
-                                      _ptr(img), _ptr(jac), nthreads)
+    jac = np.zeros((B, H, W, 4))
+    _load().orc_render_detector_jacobian(*grid.args(), _ptr(poses), B, H, W, delta_x,
+                                         delta_y, offset[0], offset[1], _ptr(img), _ptr(jac),
+                                         nthreads)
     return img, jac
 
 
-def render_fd(grid: Grid, pose, H, W, delta_x, delta_y, steps, nthreads=1):
+def render_fd(grid: Grid, pose, H, W, delta_x, delta_y, steps, nthreads=1, offset=(0.0, 0.0)):
     """Central differences of the image with respect to each pose parameter.
 
     Returns (fd [H, W, 7], kink_free [H, W, 7]): a pixel is kink-free for
@@ -188,7 +200,7 @@ def render_fd(grid: Grid, pose, H, W, delta_x, delta_y, steps, nthreads=1):
     """
     pose = _d(pose).reshape(7)
     steps = np.broadcast_to(np.asarray(steps, dtype=np.float64), (7,))
-    _, _, h0 = render(grid, pose, H, W, delta_x, delta_y, nthreads=nthreads)
+    _, _, h0 = render(grid, pose, H, W, delta_x, delta_y, nthreads=nthreads, offset=offset)
     fd = np.zeros((H, W, 7))
     ok = np.zeros((H, W, 7), dtype=bool)
     for j in range(7):
@@ -197,8 +209,8 @@ def render_fd(grid: Grid, pose, H, W, delta_x, delta_y, steps, nthreads=1):
         pp, pm = pose.copy(), pose.copy()
         pp[j] += steps[j]
         pm[j] -= steps[j]
-        ip, _, hp = render(grid, pp, H, W, delta_x, delta_y, nthreads=nthreads)
-        im, _, hm = render(grid, pm, H, W, delta_x, delta_y, nthreads=nthreads)
+        ip, _, hp = render(grid, pp, H, W, delta_x, delta_y, nthreads=nthreads, offset=offset)
+        im, _, hm = render(grid, pm, H, W, delta_x, delta_y, nthreads=nthreads, offset=offset)
         fd[:, :, j] = (ip[0] - im[0]) / (pp[j] - pm[j])
         ok[:, :, j] = (hp[0] == h0[0]) & (hm[0] == h0[0])
     return fd, ok

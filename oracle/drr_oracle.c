@@ -39,8 +39,9 @@
  *   - the image stores E itself (no exponential, no normalisation).
  *   - geometry: with R = Rz(theta) Ry(phi) Rx(gamma) and rho = sdd/2, the
  *     source is R (rho, 0, 0) + t and detector pixel (h, w) is
- *     R (-rho, u_w, v_h) + t, u_w = (w + 1/2 - W/2) delta_x,
- *     v_h = (h + 1/2 - H/2) delta_y; the image is row-major [h][w].
+ *     R (-rho, u_w, v_h) + t, u_w = (w + 1/2 - W/2) delta_x + offset_u,
+ *     v_h = (h + 1/2 - H/2) delta_y + offset_v (offsets: the detector's
+ *     principal point, 0 by default); the image is row-major [h][w].
  *   - pose vector order: (theta, phi, gamma, tx, ty, tz, sdd).
  *
  * Volume layout: C-order double array V[(i * ny + j) * nz + k], plane 0 of
@@ -127,13 +128,14 @@ static void mat_vec3(const double m[9], const double v[3], double out[3])
 
 /* Source position and the position of detector pixel (h, w). */
 void orc_ray_endpoints(const double pose[7], int H, int W, double delta_x, double delta_y,
-                       int h, int w, double s[3], double p[3])
+                       double off_u, double off_v, int h, int w, double s[3], double p[3])
 {
     double R[9];
     orc_rotation(pose[0], pose[1], pose[2], -1, R);
     double rho = 0.5 * pose[6];
     double cs[3] = {rho, 0.0, 0.0};
-    double cp[3] = {-rho, (w + 0.5 - 0.5 * W) * delta_x, (h + 0.5 - 0.5 * H) * delta_y};
+    double cp[3] = {-rho, (w + 0.5 - 0.5 * W) * delta_x + off_u,
+                    (h + 0.5 - 0.5 * H) * delta_y + off_v};
     double rs[3], rp[3];
     mat_vec3(R, cs, rs);
     mat_vec3(R, cp, rp);
@@ -146,11 +148,13 @@ void orc_ray_endpoints(const double pose[7], int H, int W, double delta_x, doubl
 /* Analytic derivatives of s and p(h, w) with respect to the seven pose
  * parameters: ds[c * 7 + j] = d s_c / d pose_j, likewise dp. */
 void orc_ray_endpoint_derivs(const double pose[7], int H, int W, double delta_x,
-                             double delta_y, int h, int w, double ds[21], double dp[21])
+                             double delta_y, double off_u, double off_v, int h, int w,
+                             double ds[21], double dp[21])
 {
     double rho = 0.5 * pose[6];
     double cs[3] = {rho, 0.0, 0.0};
-    double cp[3] = {-rho, (w + 0.5 - 0.5 * W) * delta_x, (h + 0.5 - 0.5 * H) * delta_y};
+    double cp[3] = {-rho, (w + 0.5 - 0.5 * W) * delta_x + off_u,
+                    (h + 0.5 - 0.5 * H) * delta_y + off_v};
     memset(ds, 0, 21 * sizeof(double));
     memset(dp, 0, 21 * sizeof(double));
     for (int a = 0; a < 3; ++a) {
@@ -385,8 +389,9 @@ void orc_trace_rays(const double *vol, const int32_t dims[3], const double spaci
  * so callers can evaluate a bounded sample of a large detector. */
 void orc_render(const double *vol, const int32_t dims[3], const double spacing[3],
                 const double origin[3], const double *poses /*[n][7]*/, int32_t n_poses,
-                int32_t H, int32_t W, double delta_x, double delta_y, int32_t row_begin,
-                int32_t row_end, double *image, int64_t *nseg, uint64_t *hash, int nthreads)
+                int32_t H, int32_t W, double delta_x, double delta_y, double off_u,
+                double off_v, int32_t row_begin, int32_t row_end, double *image,
+                int64_t *nseg, uint64_t *hash, int nthreads)
 {
     orc_grid g;
     grid_from(&g, vol, dims, spacing, origin);
@@ -404,7 +409,7 @@ void orc_render(const double *vol, const int32_t dims[3], const double spacing[3
             int64_t rem = r % (rows * W);
             int h = (int)(row_begin + rem / W), w = (int)(rem % W);
             double s[3], p[3];
-            orc_ray_endpoints(poses + 7 * b, H, W, delta_x, delta_y, h, w, s, p);
+            orc_ray_endpoints(poses + 7 * b, H, W, delta_x, delta_y, off_u, off_v, h, w, s, p);
             int64_t o = (b * H + h) * (int64_t)W + w;
             int64_t c = 0;
             uint64_t hh = 0;
@@ -440,8 +445,8 @@ void orc_trace_rays_grad(const double *vol, const int32_t dims[3], const double 
  * rule through the endpoint derivatives above. */
 void orc_render_jacobian(const double *vol, const int32_t dims[3], const double spacing[3],
                          const double origin[3], const double *poses, int32_t n_poses,
-                         int32_t H, int32_t W, double delta_x, double delta_y, double *image,
-                         double *jac, int nthreads)
+                         int32_t H, int32_t W, double delta_x, double delta_y, double off_u,
+                         double off_v, double *image, double *jac, int nthreads)
 {
     orc_grid g;
     grid_from(&g, vol, dims, spacing, origin);
@@ -456,8 +461,8 @@ void orc_render_jacobian(const double *vol, const int32_t dims[3], const double 
             int h = (int)((r / W) % H), w = (int)(r % W);
             const double *pose = poses + 7 * b;
             double s[3], p[3], ds[21], dp[21], gs[3], gp[3], E;
-            orc_ray_endpoints(pose, H, W, delta_x, delta_y, h, w, s, p);
-            orc_ray_endpoint_derivs(pose, H, W, delta_x, delta_y, h, w, ds, dp);
+            orc_ray_endpoints(pose, H, W, delta_x, delta_y, off_u, off_v, h, w, s, p);
+            orc_ray_endpoint_derivs(pose, H, W, delta_x, delta_y, off_u, off_v, h, w, ds, dp);
             trace_ray_grad(&g, s, p, list, &E, gs, gp);
             image[r] = E;
             for (int j = 0; j < 7; ++j) {
@@ -470,14 +475,16 @@ void orc_render_jacobian(const double *vol, const int32_t dims[3], const double 
     }
 }
 
-/* Per-pixel derivative of the image with respect to the detector pixel
- * spacing, jac[b][h][w][0..1] = d image / d (delta_x, delta_y).  The pitch
- * moves only the pixel: d p / d delta_x = R e_y (w + 1/2 - W/2) and
- * d p / d delta_y = R e_z (h + 1/2 - H/2); the source does not move. */
-void orc_render_pitch_jacobian(const double *vol, const int32_t dims[3], const double spacing[3],
-                               const double origin[3], const double *poses, int32_t n_poses,
-                               int32_t H, int32_t W, double delta_x, double delta_y,
-                               double *image, double *jac, int nthreads)
+/* Per-pixel derivative of the image with respect to the detector's
+ * intrinsic parameters: jac[b][h][w][0..3] = d image / d (delta_x, delta_y,
+ * offset_u, offset_v).  They move only the pixel, not the source:
+ * d p / d delta_x = R e_y (w + 1/2 - W/2), d p / d delta_y = R e_z
+ * (h + 1/2 - H/2), d p / d offset_u = R e_y, d p / d offset_v = R e_z. */
+void orc_render_detector_jacobian(const double *vol, const int32_t dims[3],
+                                  const double spacing[3], const double origin[3],
+                                  const double *poses, int32_t n_poses, int32_t H, int32_t W,
+                                  double delta_x, double delta_y, double off_u, double off_v,
+                                  double *image, double *jac, int nthreads)
 {
     orc_grid g;
     grid_from(&g, vol, dims, spacing, origin);
@@ -492,18 +499,20 @@ void orc_render_pitch_jacobian(const double *vol, const int32_t dims[3], const d
             int h = (int)((r / W) % H), w = (int)(r % W);
             const double *pose = poses + 7 * b;
             double s[3], p[3], gs[3], gp[3], E, R[9];
-            orc_ray_endpoints(pose, H, W, delta_x, delta_y, h, w, s, p);
+            orc_ray_endpoints(pose, H, W, delta_x, delta_y, off_u, off_v, h, w, s, p);
             trace_ray_grad(&g, s, p, list, &E, gs, gp);
             orc_rotation(pose[0], pose[1], pose[2], -1, R);
             double ku = w + 0.5 - 0.5 * W, kv = h + 0.5 - 0.5 * H;
-            double jx = 0.0, jy = 0.0;
+            double gu = 0.0, gv = 0.0;   /* gp . R e_y, gp . R e_z */
             for (int c = 0; c < 3; ++c) {
-                jx += gp[c] * R[3 * c + 1] * ku;
-                jy += gp[c] * R[3 * c + 2] * kv;
+                gu += gp[c] * R[3 * c + 1];
+                gv += gp[c] * R[3 * c + 2];
             }
             image[r] = E;
-            jac[2 * r] = jx;
-            jac[2 * r + 1] = jy;
+            jac[4 * r] = gu * ku;
+            jac[4 * r + 1] = gv * kv;
+            jac[4 * r + 2] = gu;
+            jac[4 * r + 3] = gv;
         }
         free(list);
     }

@@ -329,28 +329,48 @@ def test_render_jacobian_vs_central_differences(small_phantom):
             assert err < 1e-6, (j, err)
 
 
-def test_pitch_jacobian_vs_central_differences(small_phantom):
-    """d image / d (pixel pitch) against FP64 central differences of render()
-    in delta_x and delta_y, on pixels whose voxel sequence does not change."""
+def test_detector_jacobian_vs_central_differences(small_phantom):
+    """d image / d (delta_x, delta_y, offset_u, offset_v) against FP64 central
+    differences of render() in each detector parameter, on pixels whose voxel
+    sequence does not change, at a non-zero principal-point offset."""
     ph = small_phantom
     grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
     pose = np.array([0.2, -0.15, 0.1, 2.0, -3.0, 1.0, 1000.0])
-    H, W, dx, dy = 15, 17, 4.0, 3.5
-    img, jac = oracle.render_pitch_jacobian(grid, pose, H, W, dx, dy)
-    ref, _, h0 = oracle.render(grid, pose, H, W, dx, dy)
+    H, W, dx, dy, ou, ov = 15, 17, 4.0, 3.5, 1.3, -0.7
+    img, jac = oracle.render_detector_jacobian(grid, pose, H, W, dx, dy, offset=(ou, ov))
+    ref, _, h0 = oracle.render(grid, pose, H, W, dx, dy, offset=(ou, ov))
     np.testing.assert_allclose(img, ref, rtol=1e-13, atol=1e-13)
     e = 1e-6
-    for j, (a, b) in enumerate([((dx + e, dy), (dx - e, dy)), ((dx, dy + e), (dx, dy - e))]):
-        ip, _, hp = oracle.render(grid, pose, H, W, *a)
-        im, _, hm = oracle.render(grid, pose, H, W, *b)
+    base = np.array([dx, dy, ou, ov])
+    for j in range(4):
+        a, b = base.copy(), base.copy()
+        a[j] += e
+        b[j] -= e
+        ip, _, hp = oracle.render(grid, pose, H, W, a[0], a[1], offset=(a[2], a[3]))
+        im, _, hm = oracle.render(grid, pose, H, W, b[0], b[1], offset=(b[2], b[3]))
         fd = (ip - im)[0] / (2 * e)
         ok = ((hp == h0) & (hm == h0))[0]
         assert ok.mean() > 0.3
         scale = np.abs(jac[0, :, :, j]).max()
-        assert np.abs(jac[0, :, :, j][ok] - fd[ok]).max() < 1e-6 * scale
-        # the centre column / row does not move with the pitch
+        assert np.abs(jac[0, :, :, j][ok] - fd[ok]).max() < 1e-6 * scale, j
+    # the centre column / row does not move with the pitch
     np.testing.assert_allclose(jac[0, :, W // 2, 0], 0.0, atol=1e-9)
     np.testing.assert_allclose(jac[0, H // 2, :, 1], 0.0, atol=1e-9)
+
+
+def test_offset_by_whole_pixels_shifts_the_image(small_phantom):
+    """A principal-point offset of k pixel pitches renders the same rays as
+    the pixels k columns (rows) further on: the image shifts by k."""
+    ph = small_phantom
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    pose = np.array([-0.1, 0.25, 0.3, 1.0, 2.0, -1.5, 1000.0])
+    H, W, dx, dy = 12, 14, 2.5, 3.0
+    base, _, _ = oracle.render(grid, pose, H, W, dx, dy)
+    right, _, _ = oracle.render(grid, pose, H, W, dx, dy, offset=(3 * dx, 0.0))
+    np.testing.assert_allclose(right[0, :, :W - 3], base[0, :, 3:], rtol=1e-12, atol=1e-12)
+    up, _, _ = oracle.render(grid, pose, H, W, dx, dy, offset=(0.0, -2 * dy))
+    np.testing.assert_allclose(up[0, 2:, :], base[0, :H - 2, :], rtol=1e-12, atol=1e-12)
+    assert np.abs(right[0] - base[0]).max() > 1e-3      # the shift is not trivial
 
 
 # ---------------------------------------------------------------- ZNCC
