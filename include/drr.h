@@ -39,7 +39,8 @@
  *   R = Rz(theta) * Ry(phi) * Rx(gamma), rho = sdd / 2.
  *   source       s      = R * ( rho, 0,   0  ) + t
  *   pixel (h, w) p(h,w) = R * (-rho, u_w, v_h) + t
- *   u_w = (w + 1/2 - W/2) * delta_x,  v_h = (h + 1/2 - H/2) * delta_y.
+ *   u_w = (w + 1/2 - W/2) * delta_x + offset_u,
+ *   v_h = (h + 1/2 - H/2) * delta_y + offset_v.
  *   Images are row-major [pose][h][w] float32.
  *
  * Volume (Sec. 2.2): nx * ny * nz voxels of size spacing[0..2] (mm), plane 0
@@ -86,6 +87,8 @@ typedef struct drr_detector_desc {
     int32_t height, width; /* H rows, W columns, each >= 1 */
     double delta_x;        /* column pitch (along w), mm, > 0 */
     double delta_y;        /* row pitch (along h), mm, > 0 */
+    double offset_u;       /* principal-point offset along w, mm, finite (usually 0) */
+    double offset_v;       /* principal-point offset along h, mm, finite (usually 0) */
 } drr_detector_desc;
 
 /* ---------------------------------------------------------------- volume */
@@ -115,12 +118,16 @@ int32_t drr_render(const void* packed, const drr_volume_desc* vol, const drr_det
                    void* stream);
 
 /* Forward DRRs plus the derivative of every pixel with respect to the
- * detector pixel spacing (the paper notes these gradients exist, Sec. 3.2):
- *   jac_pitch  device float[n_poses][H][W][2] = d image / d (delta_x, delta_y)
- * (frozen voxel indices, as for the pose Jacobian). */
-int32_t drr_render_pitch_jacobian(const void* packed, const drr_volume_desc* vol,
-                                  const drr_detector_desc* det, const float* poses,
-                                  int32_t n_poses, float* image, float* jac_pitch, void* stream);
+ * detector's intrinsic parameters (the paper notes gradients with respect to
+ * the pixel spacing exist, Sec. 3.2):
+ *   jac_det  device float[n_poses][H][W][4]
+ *            = d image / d (delta_x, delta_y, offset_u, offset_v)
+ * (frozen voxel indices, as for the pose Jacobian).  These parameters move
+ * the pixel, not the source. */
+int32_t drr_render_detector_jacobian(const void* packed, const drr_volume_desc* vol,
+                                     const drr_detector_desc* det, const float* poses,
+                                     int32_t n_poses, float* image, float* jac_det,
+                                     void* stream);
 
 /* Forward DRRs plus, per pixel, the number of positive-length segments
  * (= voxel gathers) the ray made: counts device int32[n_poses][H][W]. */

@@ -9,7 +9,7 @@ the first call does, and raises if it is missing.
 
 from .drr import (Detector, Volume, drr, momentum_step, ncc_loss, render, render_backward,
                   render_backward_retrace, render_count, render_l2, render_ncc_grad,
-                  render_ncc_loss, render_pitch_jacobian)
+                  render_ncc_loss, render_detector_jacobian)
 
 __all__ = [
     "Detector",
@@ -24,5 +24,5 @@ __all__ = [
     "render_l2",
     "render_ncc_grad",
     "render_ncc_loss",
-    "render_pitch_jacobian",
+    "render_detector_jacobian",
 ]

@@ -39,7 +39,8 @@ class VolumeDesc(ctypes.Structure):
 
 class DetectorDesc(ctypes.Structure):
     _fields_ = [("height", ctypes.c_int32), ("width", ctypes.c_int32),
-                ("delta_x", ctypes.c_double), ("delta_y", ctypes.c_double)]
+                ("delta_x", ctypes.c_double), ("delta_y", ctypes.c_double),
+                ("offset_u", ctypes.c_double), ("offset_v", ctypes.c_double)]
 
 
 class WorkItem(ctypes.Structure):
@@ -70,7 +71,7 @@ SIGNATURES = {
     "drr_volume_pack": (_I32, [_V, _V, _VD, _V]),
     "drr_render": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
     "drr_render_count": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
-    "drr_render_pitch_jacobian": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
+    "drr_render_detector_jacobian": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V]),
     "drr_backward_workspace_bytes": (_SZ, [_DD, _I32]),
     "drr_render_backward": (_I32, [_DD, _I32, _V, _V, _V, _V, _SZ, _V]),
     "drr_render_backward_retrace": (_I32, [_V, _VD, _DD, _V, _I32, _V, _V, _V, _SZ, _V]),
@@ -143,8 +144,9 @@ def volume_desc(shape, spacing, origin, layout=DRR_LAYOUT_INPUT) -> VolumeDesc:
     return d
 
 
-def detector_desc(height, width, delta_x, delta_y) -> DetectorDesc:
+def detector_desc(height, width, delta_x, delta_y, offset_u=0.0, offset_v=0.0) -> DetectorDesc:
     d = DetectorDesc()
     d.height, d.width = int(height), int(width)
     d.delta_x, d.delta_y = float(delta_x), float(delta_y)
+    d.offset_u, d.offset_v = float(offset_u), float(offset_v)
     return d

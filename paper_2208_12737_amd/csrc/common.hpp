@@ -98,6 +98,8 @@ inline int32_t validate_detector(const drr_detector_desc* d)
         return fail(DRR_ENOTSUP, "detector of %d x %d pixels is too large", d->height, d->width);
     if (!finite_pos(d->delta_x) || !finite_pos(d->delta_y))
         return fail(DRR_EINVAL, "detector pitch must be finite and > 0");
+    if (!isfinite(d->offset_u) || !isfinite(d->offset_v))
+        return fail(DRR_EINVAL, "detector offsets must be finite");
     return DRR_OK;
 }
 
@@ -130,6 +132,8 @@ inline DetArgs det_args(const drr_detector_desc& d)
     a.W = d.width;
     a.dx = d.delta_x;
     a.dy = d.delta_y;
+    a.ou = d.offset_u;
+    a.ov = d.offset_v;
     return a;
 }
 

@@ -177,16 +177,17 @@ int32_t drr_render(const void* packed, const drr_volume_desc* vol, const drr_det
                                nullptr, 0, nullptr, as_stream(stream));
 }
 
-int32_t drr_render_pitch_jacobian(const void* packed, const drr_volume_desc* vol,
-                                  const drr_detector_desc* det, const float* poses,
-                                  int32_t n_poses, float* image, float* jac_pitch, void* stream)
+int32_t drr_render_detector_jacobian(const void* packed, const drr_volume_desc* vol,
+                                     const drr_detector_desc* det, const float* poses,
+                                     int32_t n_poses, float* image, float* jac_det,
+                                     void* stream)
 {
     int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
     if (st) return st;
     if (n_poses == 0) return DRR_OK;
-    if (!image || !jac_pitch) return fail(DRR_EINVAL, "render_pitch_jacobian: NULL output");
-    return launch_flat<kJacPitch>(packed, *vol, *det, poses, n_poses, image, jac_pitch, nullptr,
-                                  nullptr, 0, nullptr, as_stream(stream));
+    if (!image || !jac_det) return fail(DRR_EINVAL, "render_detector_jacobian: NULL output");
+    return launch_flat<kJacDet>(packed, *vol, *det, poses, n_poses, image, jac_det, nullptr,
+                                nullptr, 0, nullptr, as_stream(stream));
 }
 
 int32_t drr_render_count(const void* packed, const drr_volume_desc* vol,

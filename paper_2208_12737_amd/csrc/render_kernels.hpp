@@ -14,7 +14,8 @@
 //             pose gradient: I, I^2, T, T^2, IT, J[7], T J[7], I J[7]
 //   kNccLoss  image (optional) + per-tile sums for the ZNCC loss only:
 //             I, I^2, T, T^2, IT
-//   kJacPitch image + per-pixel d image / d (delta_x, delta_y) (2 floats)
+//   kJacDet   image + per-pixel d image / d (delta_x, delta_y, offset_u,
+//             offset_v) (4 floats)
 //   kL2       image (optional) + per-tile sums for the mean squared
 //             difference and its pose gradient: (I-T)^2, (I-T) J[7]
 //   kL2Loss   image (optional) + per-tile sum of (I-T)^2
@@ -25,14 +26,14 @@
 namespace drr {
 
 enum Mode { kImage = 0, kCount = 1, kJac = 2, kRetrace = 3, kNcc = 4, kNccLoss = 5,
-            kJacPitch = 6, kL2 = 7, kL2Loss = 8 };
+            kJacDet = 6, kL2 = 7, kL2Loss = 8 };
 
 constexpr int kNccSums = 26;
 
 template <int MODE>
 struct ModeTraits {
     static constexpr bool jac =
-        MODE == kJac || MODE == kRetrace || MODE == kNcc || MODE == kJacPitch || MODE == kL2;
+        MODE == kJac || MODE == kRetrace || MODE == kNcc || MODE == kJacDet || MODE == kL2;
     static constexpr bool count = MODE == kCount;
     static constexpr int nsum =
         MODE == kRetrace ? 7
@@ -95,8 +96,8 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
 
     const PoseTrig q = pose_trig(pose);
     const Mat3 R = rotation(q.ct, q.st, q.cp, q.sp, q.cg, q.sg, -1);
-    const double u = ((double)w + 0.5 - 0.5 * (double)D.W) * (double)D.dx;
-    const double v = ((double)h + 0.5 - 0.5 * (double)D.H) * (double)D.dy;
+    const double u = ((double)w + 0.5 - 0.5 * (double)D.W) * (double)D.dx + D.ou;
+    const double v = ((double)h + 0.5 - 0.5 * (double)D.H) * (double)D.dy + D.ov;
     double s[3], d[3];
     ray_of(q, R, u, v, s, d);
 
@@ -138,18 +139,18 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
     const float E = r.valid ? (float)(L * r.sum) : __builtin_nanf("");
     const int64_t pix = (int64_t)h * D.W + w;
 
-    float J[7], Jp[2];
+    float J[7], Jp[4];
     if (T::jac) {
         if (inside && r.valid) {
             // the pose frame is rebuilt here rather than kept in registers
             // through the traversal loop
             const PoseTrig q2 = pose_trig(launder(pose));
-            ray_jacobian(r, q2, u, v, J, MODE == kJacPitch ? Jp : nullptr,
+            ray_jacobian(r, q2, u, v, J, MODE == kJacDet ? Jp : nullptr,
                          (double)w + 0.5 - 0.5 * (double)D.W, (double)h + 0.5 - 0.5 * (double)D.H);
         } else {
 #pragma unroll
             for (int j = 0; j < 7; ++j) J[j] = inside ? __builtin_nanf("") : 0.0f;
-            Jp[0] = Jp[1] = inside ? __builtin_nanf("") : 0.0f;
+            Jp[0] = Jp[1] = Jp[2] = Jp[3] = inside ? __builtin_nanf("") : 0.0f;
         }
     }
 
@@ -160,9 +161,9 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
 #pragma unroll
             for (int j = 0; j < 7; ++j) o.jac[pix * 7 + j] = J[j];
         }
-        if (MODE == kJacPitch) {
-            o.jac[pix * 2] = Jp[0];
-            o.jac[pix * 2 + 1] = Jp[1];
+        if (MODE == kJacDet) {
+#pragma unroll
+            for (int j = 0; j < 4; ++j) o.jac[pix * 4 + j] = Jp[j];
         }
     }
 
@@ -225,7 +226,7 @@ __global__ __launch_bounds__(64 * WX * WY) void render_flat(
     const int64_t hw = (int64_t)D.H * D.W;
     TileOut o;
     o.image = image ? image + b * hw : nullptr;
-    o.jac = jac ? jac + b * hw * (MODE == kJacPitch ? 2 : 7) : nullptr;
+    o.jac = jac ? jac + b * hw * (MODE == kJacDet ? 4 : 7) : nullptr;
     o.counts = counts ? counts + b * hw : nullptr;
     o.aux = aux ? aux + b * aux_stride : nullptr;
     o.partial = T::nsum > 0 ? partials + ((int64_t)b * wg_per_pose + t) * T::nsum : nullptr;

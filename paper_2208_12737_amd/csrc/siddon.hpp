@@ -51,7 +51,8 @@ struct VolArgs {
 };
 
 struct DetArgs {
-    double dx, dy;
+    double dx, dy;   // pitch
+    double ou, ov;   // principal-point offset
     int32_t H, W;
 };
 
@@ -399,9 +400,10 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
 // evaluated as row-vector x matrix products so that no 3 x 3 matrix is
 // held in registers.
 //
-// With `Jp`, also the derivative with respect to the pixel pitch: the pixel
-// moves by R e_y (w + 1/2 - W/2) per unit delta_x and R e_z (h + 1/2 - H/2)
-// per unit delta_y, the source not at all, so dE = g_d . d' with
+// With `Jp`, also the derivatives with respect to the detector's pitch and
+// principal-point offset: the pixel moves by R e_y (w + 1/2 - W/2) per unit
+// delta_x, R e_z (h + 1/2 - H/2) per unit delta_y, R e_y per unit offset_u
+// and R e_z per unit offset_v, the source not at all, so dE = g_d . d' with
 // R e_y = Z Y (0, cg, sg), R e_z = Z Y (0, -sg, cg); ku, kv are the factors.
 __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, double u, double v,
                                     float J[7], float* Jp = nullptr, double ku = 0.0,
@@ -458,8 +460,12 @@ __device__ inline void ray_jacobian(const RayAcc& r, const PoseTrig& q, double u
     J[5] = (float)gs[2];
     J[6] = (float)((0.5 * gsz0 - gdz0) * ye0 + (0.5 * gs[2] - gd[2]) * ye2);
     if (Jp) {
-        Jp[0] = (float)(ku * (gdz0 * sp * sg + gdz1 * cg + gd[2] * cp * sg));
-        Jp[1] = (float)(kv * (gdz0 * sp * cg - gdz1 * sg + gd[2] * cp * cg));
+        const double gu = gdz0 * sp * sg + gdz1 * cg + gd[2] * cp * sg;   // g_d . R e_y
+        const double gv = gdz0 * sp * cg - gdz1 * sg + gd[2] * cp * cg;   // g_d . R e_z
+        Jp[0] = (float)(ku * gu);
+        Jp[1] = (float)(kv * gv);
+        Jp[2] = (float)gu;
+        Jp[3] = (float)gv;
     }
 }
 

@@ -39,15 +39,20 @@ def _poses(poses: torch.Tensor) -> torch.Tensor:
 @dataclass(frozen=True)
 class Detector:
     """Detector of height x width pixels; delta_x / delta_y are the column /
-    row pitches in mm."""
+    row pitches in mm, offset_u / offset_v the principal-point offset in mm
+    (pixel (h, w) sits at ((w + 1/2 - W/2) delta_x + offset_u,
+    (h + 1/2 - H/2) delta_y + offset_v) on the detector plane)."""
     height: int
     width: int
     delta_x: float
     delta_y: float
+    offset_u: float = 0.0
+    offset_v: float = 0.0
 
     @property
     def desc(self) -> _lib.DetectorDesc:
-        return _lib.detector_desc(self.height, self.width, self.delta_x, self.delta_y)
+        return _lib.detector_desc(self.height, self.width, self.delta_x, self.delta_y,
+                                  self.offset_u, self.offset_v)
 
     @property
     def pixels(self) -> int:
@@ -109,13 +114,14 @@ def render(volume: Volume, poses: torch.Tensor, det: Detector, jacobian: bool = 
     return (img, jac) if jacobian else img
 
 
-def render_pitch_jacobian(volume: Volume, poses: torch.Tensor, det: Detector):
-    """DRRs [n, H, W] and d image / d (delta_x, delta_y) [n, H, W, 2]."""
+def render_detector_jacobian(volume: Volume, poses: torch.Tensor, det: Detector):
+    """DRRs [n, H, W] and d image / d (delta_x, delta_y, offset_u, offset_v)
+    [n, H, W, 4]."""
     p = _poses(poses)
     n = p.shape[0]
     img = torch.empty((n, det.height, det.width), dtype=torch.float32, device=p.device)
-    jac = torch.empty((n, det.height, det.width, 2), dtype=torch.float32, device=p.device)
-    _lib.call("drr_render_pitch_jacobian", volume.packed.data_ptr(), ctypes.byref(volume.desc),
+    jac = torch.empty((n, det.height, det.width, 4), dtype=torch.float32, device=p.device)
+    _lib.call("drr_render_detector_jacobian", volume.packed.data_ptr(), ctypes.byref(volume.desc),
               ctypes.byref(det.desc), p.data_ptr(), n, img.data_ptr(), jac.data_ptr(),
               _stream())
     return img, jac

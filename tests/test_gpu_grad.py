@@ -328,27 +328,39 @@ def test_momentum_step():
     np.testing.assert_allclose(pt.cpu().numpy(), p - r * v2, rtol=1e-5, atol=1e-6)
 
 
-def test_pitch_jacobian_matches_oracle_and_differences(small):
-    """d image / d (pixel pitch): against the oracle's analytic derivative and
-    against FP64 central differences in the pitch on kink-free pixels."""
+def test_detector_jacobian_matches_oracle_and_differences(small):
+    """d image / d (delta_x, delta_y, offset_u, offset_v) at a non-zero
+    principal-point offset: against the oracle's analytic derivative and
+    against FP64 central differences of the oracle on kink-free pixels."""
     import paper_2208_12737_amd as P
     ph, vol, grid = small
     poses = random_poses(2, math.pi / 8, 10.0, 1000.0, seed=13)
-    H, W, dx, dy = 33, 29, 3.0, 2.5
-    det = P.Detector(H, W, dx, dy)
-    img, jp = P.render_pitch_jacobian(vol, _gpu(poses), det)
-    rimg, rjp = oracle.render_pitch_jacobian(grid, poses.astype(np.float64), H, W, dx, dy)
+    H, W, dx, dy, ou, ov = 33, 29, 3.0, 2.5, 4.2, -2.9
+    det = P.Detector(H, W, dx, dy, ou, ov)
+    img, jd = P.render_detector_jacobian(vol, _gpu(poses), det)
+    rimg, rjd = oracle.render_detector_jacobian(grid, poses.astype(np.float64), H, W, dx, dy,
+                                                offset=(ou, ov))
     assert_image_close(img.cpu().numpy(), rimg)
-    jp = jp.cpu().numpy()
-    scale = np.abs(rjp).max(axis=(0, 1, 2))
-    assert np.all(np.abs(jp - rjp).max(axis=(0, 1, 2)) <= JAC_RTOL * scale)
+    jd = jd.cpu().numpy()
+    scale = np.abs(rjd).max(axis=(0, 1, 2))
+    assert np.all(np.abs(jd - rjd).max(axis=(0, 1, 2)) <= JAC_RTOL * scale)
     e = 1e-3
     p0 = poses[0].astype(np.float64)
-    _, _, h0 = oracle.render(grid, p0, H, W, dx, dy)
-    for j, (a, b) in enumerate([((dx + e, dy), (dx - e, dy)), ((dx, dy + e), (dx, dy - e))]):
-        ip, _, hp = oracle.render(grid, p0, H, W, *a)
-        im, _, hm = oracle.render(grid, p0, H, W, *b)
+    base = np.array([dx, dy, ou, ov])
+    _, _, h0 = oracle.render(grid, p0, H, W, dx, dy, offset=(ou, ov))
+    for j in range(4):
+        a, b = base.copy(), base.copy()
+        a[j] += e
+        b[j] -= e
+        ip, _, hp = oracle.render(grid, p0, H, W, a[0], a[1], offset=(a[2], a[3]))
+        im, _, hm = oracle.render(grid, p0, H, W, b[0], b[1], offset=(b[2], b[3]))
         ok = ((hp == h0) & (hm == h0))[0]
         fd = (ip - im)[0] / (2 * e)
-        err = np.abs(jp[0, :, :, j][ok] - fd[ok]).max() / np.abs(fd[ok]).max()
+        err = np.abs(jd[0, :, :, j][ok] - fd[ok]).max() / np.abs(fd[ok]).max()
         assert err <= FD_RTOL, (j, err)
+    # pose Jacobian and the fused gradient with the offset detector
+    _, jac = P.render(vol, _gpu(poses), det, jacobian=True)
+    _, rjac = oracle.render_jacobian(grid, poses.astype(np.float64), H, W, dx, dy,
+                                     offset=(ou, ov))
+    errs = column_errors(jac.cpu().numpy(), rjac)
+    assert max(errs) <= JAC_RTOL, errs
