@@ -720,6 +720,48 @@ def main():
         del flush
     cold = np.array(cold)
 
+    # the differentiable-render workload: 64 poses on a 200 x 200 detector,
+    # -ZNCC against a target and d loss / d pose, three ways
+    c3 = None
+    if args.latency_reps > 0:
+        det3 = P.Detector(200, 200, pitch, pitch)
+        gt3 = random_poses(1, math.pi / 6, 30.0, sdd, seed=40)
+        off3 = np.random.default_rng(41).uniform(-1, 1, (64, 7)).astype(np.float32)
+        off3[:, :3] *= math.radians(15.0)
+        off3[:, 3:6] *= 25.0
+        off3[:, 6] = 0.0
+        mov3 = torch.from_numpy(gt3 + off3).to(dev)
+        tgt3 = P.render(vol, torch.from_numpy(gt3).to(dev), det3)[0]
+        ws3 = torch.empty(L.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det3.desc), 64),
+                          dtype=torch.uint8, device=dev)
+
+        def c3_fused():
+            P.render_ncc_grad(vol, mov3, det3, tgt3, workspace=ws3)
+
+        def c3_autograd(retrace):
+            p = mov3.clone().requires_grad_(True)
+            P.ncc_loss(P.drr(vol, p, det3, retrace=retrace), tgt3).sum().backward()
+
+        def t_med(f, reps):
+            for _ in range(3):
+                f()
+            out = []
+            for _ in range(reps):
+                a = torch.cuda.Event(enable_timing=True)
+                b = torch.cuda.Event(enable_timing=True)
+                a.record()
+                f()
+                b.record()
+                torch.cuda.synchronize()
+                out.append(a.elapsed_time(b))
+            return float(np.median(out))
+        fused = t_med(c3_fused, 50)
+        stored = t_med(lambda: c3_autograd(False), 20)
+        retr = t_med(lambda: c3_autograd(True), 20)
+        c3 = {"poses": 64, "detector": [200, 200],
+              "fused_render_ncc_grad_ms": fused, "fused_drrs_per_s": 64e3 / fused,
+              "autograd_stored_jacobian_ms": stored, "autograd_retrace_ms": retr}
+
     res = {"metric": METRIC, "unit": "DRRs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": float(step_ms.mean()),
            "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
@@ -774,6 +816,8 @@ def main():
                                            "max": float(cold.max()),
                                            "note": "device time (HIP events) after a 512 MiB "
                                                    "write that evicts L2 and Infinity Cache"}
+    if c3 is not None:
+        res["differentiable_render_64x200x200"] = c3
     res["wall_s_timed"] = wall
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)
