@@ -124,12 +124,19 @@ __device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
     r.a0 = r.a1 = r.a2 = r.b0 = r.b1 = r.b2 = 0.0f;
     r.nseg = 0;
     r.valid = true;
+    // Axis whose Jacobian sums are derived from the identities: the
+    // principal axis of the wave's first ray.  The wave's rays are a few
+    // pixels apart, so |d| / |d_c| stays below ~sqrt(3) for all of them,
+    // however wide the detector's fan.
+    const double e0 = fabs(d[0]), e1 = fabs(d[1]), e2 = fabs(d[2]);
+    const int derived =
+        __builtin_amdgcn_readfirstlane((e0 >= e1 && e0 >= e2) ? 0 : (e1 >= e2 ? 1 : 2));
     if (inside) {
         if (!T::jac)
             r = trace<false, T::count, 0>(V, rsrc, pitch, s, d);
-        else if (__builtin_amdgcn_readfirstlane(principal) == 0)
+        else if (derived == 0)
             r = trace<T::jac, T::count, 0>(V, rsrc, pitch, s, d);
-        else if (__builtin_amdgcn_readfirstlane(principal) == 1)
+        else if (derived == 1)
             r = trace<T::jac, T::count, 1>(V, rsrc, pitch, s, d);
         else
             r = trace<T::jac, T::count, 2>(V, rsrc, pitch, s, d);

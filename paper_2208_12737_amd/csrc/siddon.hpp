@@ -125,9 +125,9 @@ __device__ inline void ray_of(const PoseTrig& q, const Mat3& R, double u, double
 // are summed in the loop; the third follows from sum_k (V_before - V_after)
 // = 0 and sum_k alpha_k (V_before - V_after) = E/|d| over all crossings.  That third axis carries the rounding
 // error of the other two, which the tail multiplies by |d| / |d_c|, so it is
-// the pose's principal axis (|d| / |d_c| <= ~2.5 for every ray of a pose);
-// deriving an axis whose planes a ray runs almost parallel to would multiply
-// the error by millions.
+// the principal axis of the wave's first ray (|d| / |d_c| <= ~sqrt(3) for
+// the wave's rays); deriving an axis whose planes a ray runs almost parallel
+// to would multiply the error by millions.
 struct RayAcc {
     double sum;
     float a0, a1, a2, b0, b1, b2;
@@ -153,8 +153,8 @@ __device__ inline double min_nn(double a, double b)
 }
 
 // DERIVED is the axis whose Jacobian sums come from the identities rather
-// than the loop: the principal axis of the pose's central ray, so that
-// |d| / |d_DERIVED| stays small for every ray of the pose.  (A template
+// than the loop: the principal axis of the wave's first ray, so that
+// |d| / |d_DERIVED| stays small for every ray of the wave.  (A template
 // argument: with a run-time axis the compiler selects between the per-lane
 // crossing masks with several VALU instructions per step.)
 template <bool JAC, bool COUNT, int DERIVED>
