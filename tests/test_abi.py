@@ -91,3 +91,27 @@ def test_plan_rejects_bad_descriptors():
     assert lib.drr_plan_create(ctypes.byref(desc), None, 0, None,
                                ctypes.byref(out)) == _lib.DRR_EINVAL
     assert lib.drr_plan_execute(None, None, 0, None) == _lib.DRR_EINVAL
+
+
+def test_missing_library_fails_loudly(tmp_path):
+    """Without libdrr.so the first call raises; nothing falls back to a CPU
+    path."""
+    import subprocess
+    import sys
+    code = ("import paper_2208_12737_amd._lib as L; L.LIB_PATH = %r\n"
+            "try:\n    L.load()\nexcept ImportError as e:\n    print('raised', e)\n"
+            % str(tmp_path / "absent.so"))
+    r = subprocess.run([sys.executable, "-c", code], capture_output=True, text=True, cwd=ROOT,
+                       timeout=120)
+    assert r.returncode == 0 and r.stdout.startswith("raised"), r.stdout + r.stderr
+
+
+def test_product_never_reaches_the_oracle():
+    """The package neither imports nor loads anything from oracle/."""
+    pkg = os.path.join(ROOT, "paper_2208_12737_amd")
+    for dirpath, _, files in os.walk(pkg):
+        for f in files:
+            if f.endswith((".py", ".hip", ".hpp", ".h")):
+                text = open(os.path.join(dirpath, f)).read()
+                assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
+                assert "liboracle" not in text and "drr_oracle" not in text, f
