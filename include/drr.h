@@ -238,16 +238,28 @@ int32_t drr_pose_momentum_step(float* poses, float* velocity, const float* grad_
 
 #define DRR_ITEM_JAC 1      /* also write the Jacobian to item.jac */
 #define DRR_ITEM_COUNT 2    /* also write per-pixel gather counts to item.counts */
+#define DRR_ITEM_NCC 4      /* fused objective: -ZNCC against item.target and its pose
+                               gradient, as drr_render_ncc_grad (no Jacobian stored) */
 
 typedef struct drr_work_item {
     int32_t volume;          /* index into the plan's volume table */
-    int32_t flags;           /* DRR_ITEM_* */
+    int32_t flags;           /* DRR_ITEM_*; at most one of JAC, COUNT, NCC */
     drr_detector_desc det;
     const float* pose;       /* device float[7] */
-    float* image;            /* device float[H][W] */
+    float* image;            /* device float[H][W]; may be NULL for DRR_ITEM_NCC */
     float* jac;              /* device float[H][W][7] when DRR_ITEM_JAC */
     int32_t* counts;         /* device int32[H][W] when DRR_ITEM_COUNT */
+    const float* target;     /* device float[H][W] when DRR_ITEM_NCC */
+    float* loss;             /* device float[1] when DRR_ITEM_NCC: -ZNCC */
+    float* grad;             /* device float[7] when DRR_ITEM_NCC: d loss / d pose */
+    double* partials;        /* device scratch of drr_plan_item_workspace_bytes(&det)
+                                bytes when DRR_ITEM_NCC, private to the item until
+                                the execute completes */
 } drr_work_item;
+
+/* Scratch bytes a DRR_ITEM_NCC item needs for its detector (enough for any
+ * launch shape the plan may use); 0 for an invalid detector. */
+size_t drr_plan_item_workspace_bytes(const drr_detector_desc* det);
 
 typedef struct drr_plan_desc {
     int32_t max_items;                   /* capacity of one execute call */

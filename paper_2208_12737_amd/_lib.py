@@ -21,6 +21,7 @@ DRR_EHIP = -3
 DRR_ENOTSUP = -4
 DRR_ITEM_JAC = 1
 DRR_ITEM_COUNT = 2
+DRR_ITEM_NCC = 4
 DRR_PLAN_PERSISTENT = 0
 DRR_PLAN_FLAT = 1
 
@@ -46,7 +47,8 @@ class DetectorDesc(ctypes.Structure):
 class WorkItem(ctypes.Structure):
     _fields_ = [("volume", ctypes.c_int32), ("flags", ctypes.c_int32), ("det", DetectorDesc),
                 ("pose", ctypes.c_void_p), ("image", ctypes.c_void_p), ("jac", ctypes.c_void_p),
-                ("counts", ctypes.c_void_p)]
+                ("counts", ctypes.c_void_p), ("target", ctypes.c_void_p), ("loss", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("partials", ctypes.c_void_p)]
 
 
 class PlanDesc(ctypes.Structure):
@@ -91,6 +93,7 @@ SIGNATURES = {
     "drr_plan_config": (_I32, [_V, ctypes.POINTER(_I32), ctypes.POINTER(_I32),
                                ctypes.POINTER(_I32), ctypes.POINTER(_I32)]),
     "drr_plan_destroy": (None, [_V]),
+    "drr_plan_item_workspace_bytes": (_SZ, [_DD]),
     "drr_set_launch_occupancy": (_I32, [_I32]),
     "drr_status_string": (ctypes.c_char_p, [_I32]),
     "drr_last_error": (ctypes.c_char_p, []),

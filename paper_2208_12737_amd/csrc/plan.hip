@@ -4,8 +4,11 @@
 // shape chosen by timing candidates (autotuner).
 //
 // Queues.  Each execute call groups its items by output mode (image /
-// image + counts / image + Jacobian) and lays the tiles of each group out
-// item after item.  The tile range of a group is split into 8 contiguous
+// image + counts / image + Jacobian / fused -ZNCC objective) and lays the
+// tiles of each group out item after item.  Items of the objective group
+// write per-tile moment sums to their own scratch; a finalize kernel, one
+// workgroup per item, then reduces them in a fixed order into the item's
+// loss and pose gradient.  The tile range of a group is split into 8 contiguous
 // shares, one per XCD; a workgroup first drains the share of the XCD it
 // runs on (hardware dispatch is round-robin over the XCDs), so concurrently
 // running workgroups of one XCD render neighbouring tiles of one pose and
@@ -23,11 +26,11 @@
 #include <vector>
 
 #include "common.hpp"
-#include "render_kernels.hpp"
+#include "reduce_common.hpp"
 
 namespace drr {
 
-constexpr int kPlanModes = 3;   // kImage, kCount, kJac
+constexpr int kPlanModes = 4;   // groups: kImage, kCount, kJac, kNcc (see group_mode)
 constexpr int kXcds = 8;
 constexpr int kRing = 4;        // item tables in flight
 constexpr int kMaxPlanItems = 8192;
@@ -39,10 +42,21 @@ struct PlanItem {
     float* image;
     float* jac;
     int32_t* counts;
+    const float* target;  // objective items
+    float* loss;
+    float* grad;
+    double* partials;     // [tiles][kNccSums]
     int32_t tiles_x;
     int32_t tile_begin;   // first tile of this item within its group
-    int32_t pad[2];
+    int32_t tiles;        // tiles of this item
+    int32_t pad;
 };
+
+// Render mode of group g (groups are indexed 0..kPlanModes-1).
+__host__ __device__ constexpr int group_mode(int g)
+{
+    return g == 0 ? kImage : (g == 1 ? kCount : (g == 2 ? kJac : kNcc));
+}
 
 struct PlanHeader {
     int32_t first[kPlanModes];   // first item of each group
@@ -88,7 +102,7 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
 {
     using S = TileShape<TW, WX, WY>;
     __shared__ int s_tile;
-    __shared__ double lds[1];
+    __shared__ double lds[MODE == kNcc ? kNccSums * WX * WY : 1];
     const PlanHeader* hdr = (const PlanHeader*)block;
     const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
     const int first = hdr->first[group], count = hdr->count[group], total = hdr->tiles[group];
@@ -117,8 +131,8 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
         o.image = it.image;
         o.jac = it.jac;
         o.counts = it.counts;
-        o.aux = nullptr;
-        o.partial = nullptr;
+        o.aux = MODE == kNcc ? it.target : nullptr;
+        o.partial = MODE == kNcc ? it.partials + (int64_t)local * kNccSums : nullptr;
         render_tile<TW, WX, WY, MODE>(it.vol, it.det, it.pose, tx, ty, o, lds);
     }
     (void)sizeof(S);
@@ -131,7 +145,7 @@ template <int TW, int WX, int WY, int MODE>
 __global__ __launch_bounds__(64 * WX * WY) void render_plan_flat(const char* __restrict__ block,
                                                                  int group)
 {
-    __shared__ double lds[1];
+    __shared__ double lds[MODE == kNcc ? kNccSums * WX * WY : 1];
     const PlanHeader* hdr = (const PlanHeader*)block;
     const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
     const int first = hdr->first[group], count = hdr->count[group];
@@ -149,9 +163,22 @@ __global__ __launch_bounds__(64 * WX * WY) void render_plan_flat(const char* __r
     o.image = it.image;
     o.jac = it.jac;
     o.counts = it.counts;
-    o.aux = nullptr;
-    o.partial = nullptr;
+    o.aux = MODE == kNcc ? it.target : nullptr;
+    o.partial = MODE == kNcc ? it.partials + (int64_t)local * kNccSums : nullptr;
     render_tile<TW, WX, WY, MODE>(it.vol, it.det, it.pose, tx, ty, o, lds);
+}
+
+// Loss and pose gradient of every objective item: workgroup i reduces the
+// tile sums of item first + i in a fixed order.
+__global__ __launch_bounds__(kReduceThreads) void k_plan_ncc_finalize(
+    const char* __restrict__ block, int group)
+{
+    __shared__ double lds[kReduceThreads * kNccSums];
+    const PlanHeader* hdr = (const PlanHeader*)block;
+    const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
+    const PlanItem& it = items[hdr->first[group] + (int)blockIdx.x];
+    sum_tile_partials<kNccSums>(it.partials, it.tiles, lds);
+    ncc_from_sums(lds, (double)it.det.H * (double)it.det.W, it.loss, it.grad);
 }
 
 // ------------------------------------------------------------------ shapes
@@ -191,11 +218,14 @@ static PersistentFn persistent_fn(int code)
     }
 }
 
-static PersistentFn kernel_for(int mode, int code)
+static PersistentFn kernel_for(int group, int code)
 {
-    if (mode == kImage) return persistent_fn<kImage>(code);
-    if (mode == kCount) return persistent_fn<kCount>(code);
-    return persistent_fn<kJac>(code);
+    switch (group_mode(group)) {
+    case kImage: return persistent_fn<kImage>(code);
+    case kCount: return persistent_fn<kCount>(code);
+    case kJac: return persistent_fn<kJac>(code);
+    default: return persistent_fn<kNcc>(code);
+    }
 }
 
 typedef void (*FlatFn)(const char*, int);
@@ -216,20 +246,43 @@ static FlatFn flat_fn(int code)
     }
 }
 
-static FlatFn flat_kernel_for(int mode, int code)
+static FlatFn flat_kernel_for(int group, int code)
 {
-    if (mode == kImage) return flat_fn<kImage>(code);
-    if (mode == kCount) return flat_fn<kCount>(code);
-    return flat_fn<kJac>(code);
+    switch (group_mode(group)) {
+    case kImage: return flat_fn<kImage>(code);
+    case kCount: return flat_fn<kCount>(code);
+    case kJac: return flat_fn<kJac>(code);
+    default: return flat_fn<kNcc>(code);
+    }
 }
 
 enum Strategy { kPersistent = 0, kFlat = 1 };
 
-static int mode_of_flags(int32_t flags)
+// Group of an item: 0 image, 1 image + counts, 2 image + Jacobian,
+// 3 objective.
+static int group_of_flags(int32_t flags)
 {
-    if (flags & DRR_ITEM_JAC) return kJac;
-    if (flags & DRR_ITEM_COUNT) return kCount;
-    return kImage;
+    if (flags & DRR_ITEM_NCC) return 3;
+    if (flags & DRR_ITEM_JAC) return 2;
+    if (flags & DRR_ITEM_COUNT) return 1;
+    return 0;
+}
+
+// Upper bound of the static LDS of group g's plan kernels: the tile index
+// and the block-sum buffer of the objective group.
+static size_t plan_static_lds(int g, const ShapeInfo& sh)
+{
+    return 16 + (group_mode(g) == kNcc ? sizeof(double) * kNccSums * sh.wx * sh.wy : 0);
+}
+
+// Tiles of a detector for launch shape `code`.
+static int64_t tiles_for(const drr_detector_desc& d, int code, int* tiles_x)
+{
+    const ShapeInfo& sh = kShapes[code];
+    const int pxw = sh.tw * sh.wx, pxh = (64 / sh.tw) * sh.wy;
+    const int tx = (d.width + pxw - 1) / pxw, ty = (d.height + pxh - 1) / pxh;
+    if (tiles_x) *tiles_x = tx;
+    return (int64_t)tx * ty;
 }
 
 }  // namespace drr
@@ -243,7 +296,7 @@ struct drr_plan {
     int strategy = 0;          // kPersistent or kFlat
     int tile_code = 0;
     int wg_per_cu = 0;         // requested workgroups per CU (0 = occupancy limit)
-    int grid[kPlanModes] = {0, 0, 0};   // persistent grid per mode
+    int grid[kPlanModes] = {0, 0, 0, 0};   // persistent grid per group
     int num_cus = 0;
     bool use_graph = false;
     Slot slots[kRing];
@@ -279,8 +332,6 @@ static int32_t compute_grids(drr_plan* p)
 // Fills slot `s` for the given items; returns the mode mask via *mask.
 static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int n, int* mask)
 {
-    const ShapeInfo& sh = kShapes[p->tile_code];
-    const int pxw = sh.tw * sh.wx, pxh = (64 / sh.tw) * sh.wy;
     PlanHeader* h = s.h_header;
     int pos = 0;
     *mask = 0;
@@ -290,7 +341,7 @@ static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int
         int64_t tiles = 0;
         for (int i = 0; i < n; ++i) {
             const drr_work_item& w = items[i];
-            if (mode_of_flags(w.flags) != m) continue;
+            if (group_of_flags(w.flags) != m) continue;
             PlanItem& it = s.h_items[pos++];
             it.vol = vol_args(p->packed[w.volume], p->vols[w.volume]);
             it.det = det_args(w.det);
@@ -298,10 +349,14 @@ static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int
             it.image = w.image;
             it.jac = w.jac;
             it.counts = w.counts;
-            it.tiles_x = (w.det.width + pxw - 1) / pxw;
-            const int ty = (w.det.height + pxh - 1) / pxh;
+            it.target = w.target;
+            it.loss = w.loss;
+            it.grad = w.grad;
+            it.partials = w.partials;
+            const int64_t t = tiles_for(w.det, p->tile_code, &it.tiles_x);
+            it.tiles = (int32_t)t;
             it.tile_begin = (int32_t)tiles;
-            tiles += (int64_t)it.tiles_x * ty;
+            tiles += t;
             h->count[m]++;
         }
         if (tiles > 0x7FFFFFFF) return fail(DRR_ENOTSUP, "too many tiles in one execute");
@@ -311,21 +366,30 @@ static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int
     return DRR_OK;
 }
 
+// The objective group's losses and gradients, after its tiles are rendered.
+static int32_t enqueue_finalize(Slot& s, int mask, hipStream_t st)
+{
+    constexpr int g = 3;
+    if (!(mask & (1 << g))) return DRR_OK;
+    hipLaunchKernelGGL(k_plan_ncc_finalize, dim3(s.h_header->count[g]), dim3(kReduceThreads), 0,
+                       st, (const char*)s.d_block, g);
+    return check_launch("plan objective finalize");
+}
+
 static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
 {
     const ShapeInfo& sh = kShapes[p->tile_code];
     const int threads = 64 * sh.wx * sh.wy;
     int32_t rc;
     if (p->strategy == kFlat) {
-        // the plan kernels' own LDS: a tile index and one double
-        const size_t lds = occupancy_lds(p->wg_per_cu, 16);
         for (int m = 0; m < kPlanModes; ++m) {
             if (!(mask & (1 << m))) continue;
+            const size_t lds = occupancy_lds(p->wg_per_cu, plan_static_lds(m, sh));
             hipLaunchKernelGGL(flat_kernel_for(m, p->tile_code), dim3(s.h_header->tiles[m]),
                                dim3(threads), lds, st, (const char*)s.d_block, m);
             if ((rc = check_launch("plan flat kernel"))) return rc;
         }
-        return DRR_OK;
+        return enqueue_finalize(s, mask, st);
     }
     hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, s.d_counters,
                        kPlanModes * kXcds);
@@ -336,7 +400,7 @@ static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
                            (const char*)s.d_block, s.d_counters, m);
         if ((rc = check_launch("plan persistent kernel"))) return rc;
     }
-    return DRR_OK;
+    return enqueue_finalize(s, mask, st);
 }
 
 static void drop_graphs(Slot& s)
@@ -360,7 +424,7 @@ static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hi
     hipError_t e = hipMemcpyAsync(s.d_block, s.h_header, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(DRR_EHIP, "plan table copy: %s", hipGetErrorString(e));
     if (p->use_graph && st != nullptr) {
-        std::vector<int> key = {mask};
+        std::vector<int> key = {mask, s.h_header->count[3]};
         if (p->strategy == kFlat)
             for (int m = 0; m < kPlanModes; ++m) key.push_back(s.h_header->tiles[m]);
         auto found = s.graphs.find(key);
@@ -401,12 +465,23 @@ static int32_t validate_items(const drr_plan* p, const drr_work_item* items, int
             return fail(DRR_EINVAL, "item %d: volume index %d out of range", i, w.volume);
         int32_t rc = validate_detector(&w.det);
         if (rc) return rc;
-        if (!w.pose || !w.image) return fail(DRR_EINVAL, "item %d: NULL pose or image", i);
+        if (!w.pose) return fail(DRR_EINVAL, "item %d: NULL pose", i);
+        if (!w.image && !(w.flags & DRR_ITEM_NCC))
+            return fail(DRR_EINVAL, "item %d: NULL image", i);
         if ((w.flags & DRR_ITEM_JAC) && !w.jac) return fail(DRR_EINVAL, "item %d: NULL jac", i);
         if ((w.flags & DRR_ITEM_COUNT) && !w.counts)
             return fail(DRR_EINVAL, "item %d: NULL counts", i);
-        if ((w.flags & DRR_ITEM_JAC) && (w.flags & DRR_ITEM_COUNT))
-            return fail(DRR_EINVAL, "item %d: JAC and COUNT cannot be combined", i);
+        const int kinds = ((w.flags & DRR_ITEM_JAC) ? 1 : 0) + ((w.flags & DRR_ITEM_COUNT) ? 1 : 0) +
+                          ((w.flags & DRR_ITEM_NCC) ? 1 : 0);
+        if (kinds > 1) return fail(DRR_EINVAL, "item %d: JAC, COUNT and NCC are exclusive", i);
+        if (w.flags & ~(DRR_ITEM_JAC | DRR_ITEM_COUNT | DRR_ITEM_NCC))
+            return fail(DRR_EINVAL, "item %d: unknown flags 0x%x", i, (unsigned)w.flags);
+        if (w.flags & DRR_ITEM_NCC) {
+            if (!w.target || !w.loss || !w.grad || !w.partials)
+                return fail(DRR_EINVAL, "item %d: NULL target, loss, grad or partials", i);
+            if ((int64_t)w.det.height * w.det.width < 2)
+                return fail(DRR_EINVAL, "item %d: the objective needs at least 2 pixels", i);
+        }
     }
     return DRR_OK;
 }
@@ -422,13 +497,18 @@ static std::string tune_key(const drr_plan* p, const drr_work_item* items, int n
                  v.spacing[1], v.spacing[2]);
         k += b;
     }
-    int64_t px[kPlanModes] = {0, 0, 0};
+    int64_t px[kPlanModes] = {0, 0, 0, 0};
     for (int i = 0; i < n; ++i)
-        px[mode_of_flags(items[i].flags)] += (int64_t)items[i].det.height * items[i].det.width;
-    char b[96];
+        px[group_of_flags(items[i].flags)] += (int64_t)items[i].det.height * items[i].det.width;
+    char b[128];
     snprintf(b, sizeof b, "|n%d|px%lld,%lld,%lld", n, (long long)px[0], (long long)px[1],
              (long long)px[2]);
-    return k + b;
+    k += b;
+    if (px[3] > 0) {   // older cache lines (no objective items) keep their keys
+        snprintf(b, sizeof b, ",%lld", (long long)px[3]);
+        k += b;
+    }
+    return k;
 }
 
 static bool cache_lookup(const char* path, const std::string& key, int* strategy, int* code,
@@ -640,6 +720,17 @@ int32_t drr_plan_config(const drr_plan* plan, int32_t* strategy, int32_t* tile_c
 void drr_plan_destroy(drr_plan* plan)
 {
     if (plan) free_plan(plan);
+}
+
+size_t drr_plan_item_workspace_bytes(const drr_detector_desc* det)
+{
+    if (!det || validate_detector(det) != DRR_OK) return 0;
+    int64_t most = 0;
+    for (int c = 0; c < kNumShapes; ++c) {
+        const int64_t t = tiles_for(*det, c, nullptr);
+        most = t > most ? t : most;
+    }
+    return (size_t)most * kNccSums * sizeof(double);
 }
 
 }  // extern "C"

@@ -5,11 +5,10 @@
 // bitwise reproducible and independent of what else is in the batch.
 #pragma once
 
-#include "render_kernels.hpp"
+#include "reduce_common.hpp"
 
 namespace drr {
 
-constexpr int kReduceThreads = 256;
 constexpr int kChunkPixels = 1024;   // pixels per workgroup in streaming kernels
 
 // Sums partials[b][0..n)[0..NS) over the middle index for pose b = blockIdx.x
@@ -17,23 +16,7 @@ constexpr int kChunkPixels = 1024;   // pixels per workgroup in streaming kernel
 template <int NS>
 __device__ inline void sum_partials(const double* __restrict__ partials, int n, double* lds)
 {
-    const int i = threadIdx.x;
-    const double* base = partials + (int64_t)blockIdx.x * n * NS;
-    double acc[NS];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) acc[k] = 0.0;
-    for (int t = i; t < n; t += kReduceThreads)
-#pragma unroll
-        for (int k = 0; k < NS; ++k) acc[k] += base[(int64_t)t * NS + k];
-#pragma unroll
-    for (int k = 0; k < NS; ++k) lds[i * NS + k] = acc[k];
-    __syncthreads();
-    for (int stride = kReduceThreads / 2; stride >= 1; stride >>= 1) {
-        if (i < stride)
-#pragma unroll
-            for (int k = 0; k < NS; ++k) lds[i * NS + k] += lds[(i + stride) * NS + k];
-        __syncthreads();
-    }
+    sum_tile_partials<NS>(partials + (int64_t)blockIdx.x * n * NS, n, lds);
 }
 
 // grad_pose[b][j] = sum of partials (7 values per tile).
@@ -56,18 +39,7 @@ __global__ __launch_bounds__(kReduceThreads) void k_ncc_grad_finalize(const doub
 {
     __shared__ double lds[kReduceThreads * kNccSums];
     sum_partials<kNccSums>(partials, n, lds);
-    if ((int)threadIdx.x < 7) {
-        const double* S = lds;
-        const double mi = S[0] / npix, mt = S[2] / npix;
-        const double si = sqrt(fmax(S[1] / npix - mi * mi, 0.0));
-        const double st = sqrt(fmax(S[3] / npix - mt * mt, 0.0));
-        const double z = (S[4] / npix - mi * mt) / (si * st);
-        const int j = threadIdx.x;
-        const double tj = (S[12 + j] - mt * S[5 + j]) / st;
-        const double ij = (S[19 + j] - mi * S[5 + j]) / si;
-        grad_pose[blockIdx.x * 7 + j] = (float)(-(tj - z * ij) / (npix * si));
-        if (j == 0) loss[blockIdx.x] = (float)(-z);
-    }
+    ncc_from_sums(lds, npix, loss + blockIdx.x, grad_pose + blockIdx.x * 7);
 }
 
 // Loss only, from fused tile sums (I, I^2, T, T^2, IT): loss[b] = -Z.

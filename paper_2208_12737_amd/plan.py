@@ -15,13 +15,22 @@ from .drr import Detector, Volume, _stream
 
 @dataclass
 class Item:
-    """One render: volume index, detector, a device pose [7] and outputs."""
+    """One render: volume index, detector, a device pose [7] and outputs.
+
+    An objective item (``target`` given) computes the fused -ZNCC against
+    ``target`` into ``loss`` [1] and its pose gradient into ``grad`` [7],
+    using ``partials`` (float64, ``item_workspace_bytes(det)`` bytes) as
+    scratch; its ``image`` is optional.  ``objective_item`` allocates these."""
     volume: int
     det: Detector
     pose: torch.Tensor
-    image: torch.Tensor
+    image: Optional[torch.Tensor]
     jac: Optional[torch.Tensor] = None
     counts: Optional[torch.Tensor] = None
+    target: Optional[torch.Tensor] = None
+    loss: Optional[torch.Tensor] = None
+    grad: Optional[torch.Tensor] = None
+    partials: Optional[torch.Tensor] = None
 
     def flags(self) -> int:
         f = 0
@@ -29,25 +38,68 @@ class Item:
             f |= _lib.DRR_ITEM_JAC
         if self.counts is not None:
             f |= _lib.DRR_ITEM_COUNT
+        if self.target is not None:
+            f |= _lib.DRR_ITEM_NCC
         return f
+
+
+def item_workspace_bytes(det: Detector) -> int:
+    """Scratch bytes of one objective item on detector `det`."""
+    n = int(_lib.load().drr_plan_item_workspace_bytes(ctypes.byref(det.desc)))
+    if n == 0:
+        raise ValueError(f"invalid detector {det}")
+    return n
+
+
+def objective_item(volume: int, det: Detector, pose: torch.Tensor, target: torch.Tensor,
+                   image: Optional[torch.Tensor] = None) -> Item:
+    """An objective item with freshly allocated loss, gradient and scratch."""
+    dev = pose.device
+    return Item(volume, det, pose, image, target=target,
+                loss=torch.empty(1, dtype=torch.float32, device=dev),
+                grad=torch.empty(7, dtype=torch.float32, device=dev),
+                partials=torch.empty(item_workspace_bytes(det) // 8, dtype=torch.float64,
+                                     device=dev))
+
+
+def _check(k, name, t, numel, dtype=torch.float32):
+    if not (t.is_cuda and t.dtype == dtype and t.is_contiguous()):
+        raise TypeError(f"item {k}: {name} must be a contiguous {dtype} GPU tensor")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"item {k}: {name} has {t.numel()} elements, expected {numel}")
 
 
 def _items_array(items: Sequence[Item]):
     arr = (_lib.WorkItem * max(len(items), 1))()
     for k, it in enumerate(items):
-        for t, name in ((it.pose, "pose"), (it.image, "image")):
-            if not (t.is_cuda and t.dtype == torch.float32 and t.is_contiguous()):
-                raise TypeError(f"item {k}: {name} must be a contiguous float32 GPU tensor")
-        if it.image.numel() != it.det.pixels or it.pose.numel() != 7:
-            raise ValueError(f"item {k}: image or pose has the wrong size")
+        _check(k, "pose", it.pose, 7)
+        if it.image is not None:
+            _check(k, "image", it.image, it.det.pixels)
+        elif it.target is None:
+            raise ValueError(f"item {k}: image is required")
+        if it.target is not None:
+            _check(k, "target", it.target, it.det.pixels)
+            for name in ("loss", "grad", "partials"):
+                if getattr(it, name) is None:
+                    raise ValueError(f"item {k}: objective item needs {name}")
+            _check(k, "loss", it.loss, 1)
+            _check(k, "grad", it.grad, 7)
+            _check(k, "partials", it.partials, None, torch.float64)
+            if it.partials.numel() * 8 < item_workspace_bytes(it.det):
+                raise ValueError(f"item {k}: partials smaller than item_workspace_bytes")
         w = arr[k]
         w.volume = it.volume
         w.flags = it.flags()
         w.det = it.det.desc
         w.pose = it.pose.data_ptr()
-        w.image = it.image.data_ptr()
+        w.image = it.image.data_ptr() if it.image is not None else None
         w.jac = it.jac.data_ptr() if it.jac is not None else None
         w.counts = it.counts.data_ptr() if it.counts is not None else None
+        if it.target is not None:
+            w.target = it.target.data_ptr()
+            w.loss = it.loss.data_ptr()
+            w.grad = it.grad.data_ptr()
+            w.partials = it.partials.data_ptr()
     return arr
 
 

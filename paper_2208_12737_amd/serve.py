@@ -24,7 +24,6 @@ object (``GpuBackend`` here, or a stand-in in tests).
 from __future__ import annotations
 
 import collections
-import ctypes
 import threading
 import time
 from dataclasses import dataclass, field
@@ -219,63 +218,48 @@ class GpuBackend:
         self.dev = volumes[self.names[0]].device
 
     def bytes_for(self, req: Request) -> int:
-        from . import _lib
         from .drr import Detector
+        from .plan import item_workspace_bytes
         px = req.height * req.width * 4
         if req.kind == FWD:
             return px + 64
         det = Detector(req.height, req.width, req.delta_x, req.delta_y)
-        ws = _lib.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), 1)
-        return 2 * px + ws + 64
+        return px + item_workspace_bytes(det) + 32 + 64
 
     def launch(self, tickets: List[Ticket], stream_idx: int):
+        """One plan execute for the whole batch: forward items render an
+        image, fwd+bwd items also reduce -ZNCC against their target and its
+        pose gradient in the same launch."""
         torch = self.torch
-        from . import _lib
-        from .drr import Detector, _stream
-        from .plan import Item
+        from .drr import Detector
+        from .plan import objective_item, Item
         stream = self.streams[stream_idx]
         stream.wait_stream(torch.cuda.current_stream())
         n = len(tickets)
         host = torch.empty((n, 7), dtype=torch.float32, pin_memory=True)
         host.numpy()[:] = np.stack([np.asarray(t.request.pose, np.float32) for t in tickets])
         out = {}
+        keep = []
         with torch.cuda.stream(stream):
             poses = host.to(self.dev, non_blocking=True)
-            items, fwd_idx = [], []
-            groups = collections.defaultdict(list)
+            items = []
             for k, t in enumerate(tickets):
                 r = t.request
                 det = Detector(r.height, r.width, r.delta_x, r.delta_y)
+                img = torch.empty((r.height, r.width), dtype=torch.float32, device=self.dev)
                 if r.kind == FWD:
-                    img = torch.empty((r.height, r.width), dtype=torch.float32, device=self.dev)
                     items.append(Item(self.index[r.volume], det, poses[k], img))
-                    fwd_idx.append(k)
                     out[k] = img
                 else:
-                    groups[(r.volume, r.height, r.width, r.delta_x, r.delta_y)].append(k)
-            if items:
-                self.plan.execute(items)
-            for (vname, H, W, dx, dy), ks in groups.items():
-                det = Detector(H, W, dx, dy)
-                g = len(ks)
-                idx = torch.tensor(ks, device=self.dev)
-                gp = poses.index_select(0, idx).contiguous()
-                tg = torch.stack([tickets[k].request.target.reshape(H, W) for k in ks]).contiguous()
-                loss = torch.empty((g,), dtype=torch.float32, device=self.dev)
-                grad = torch.empty((g, 7), dtype=torch.float32, device=self.dev)
-                img = torch.empty((g, H, W), dtype=torch.float32, device=self.dev)
-                nb = _lib.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), g)
-                ws = torch.empty(max(nb, 8), dtype=torch.uint8, device=self.dev)
-                vol = self.volumes[vname]
-                _lib.call("drr_render_ncc_grad", vol.packed.data_ptr(), ctypes.byref(vol.desc),
-                          ctypes.byref(det.desc), gp.data_ptr(), g, tg.data_ptr(), H * W,
-                          img.data_ptr(), loss.data_ptr(), grad.data_ptr(), ws.data_ptr(),
-                          ws.numel(), _stream())
-                for j, k in enumerate(ks):
-                    out[k] = (img[j], loss[j], grad[j])
+                    tg = r.target.reshape(r.height, r.width).contiguous()
+                    it = objective_item(self.index[r.volume], det, poses[k], tg, image=img)
+                    items.append(it)
+                    keep.append(tg)
+                    out[k] = (img, it.loss[0], it.grad)
+            self.plan.execute(items)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return (ev, out, n, host)
+        return (ev, out, n, (host, keep, items))
 
     def poll(self, h) -> bool:
         return h[0].query()

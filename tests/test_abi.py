@@ -115,3 +115,26 @@ def test_product_never_reaches_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert not re.search(r"^\s*(import|from)\s+oracle\b", text, re.M), f
                 assert "liboracle" not in text and "drr_oracle" not in text, f
+
+
+def test_plan_item_workspace_covers_every_launch_shape():
+    """Scratch of an objective item: the most tiles any plan launch shape
+    cuts the detector into (8 x 8 px tiles are the smallest), times 26
+    float64 moment sums per tile."""
+    lib = _lib.load()
+    for (h, w), tiles in (((64, 64), 64), ((37, 53), 5 * 7), ((1, 1), 1), ((256, 256), 1024)):
+        det = _lib.detector_desc(h, w, 1.0, 1.0)
+        assert lib.drr_plan_item_workspace_bytes(ctypes.byref(det)) == tiles * 26 * 8
+    bad = _lib.detector_desc(0, 8, 1.0, 1.0)
+    assert lib.drr_plan_item_workspace_bytes(ctypes.byref(bad)) == 0
+    assert lib.drr_plan_item_workspace_bytes(None) == 0
+
+
+def test_work_item_layout_matches_header():
+    """The binding's drr_work_item has the C struct's size and field offsets
+    (LP64: 6 pointers of the original layout plus 4 for objective items)."""
+    W = _lib.WorkItem
+    assert W.det.offset == 8
+    assert W.pose.offset == 8 + ctypes.sizeof(_lib.DetectorDesc)
+    assert W.partials.offset == W.pose.offset + 7 * 8
+    assert ctypes.sizeof(W) == W.partials.offset + 8

@@ -136,6 +136,124 @@ def test_plan_rejects_bad_items(vols):
     plan.close()
 
 
+def _objective_items(P, vs, seed, n=10):
+    """Objective items mixed with image and Jacobian items; targets are DRRs
+    at perturbed poses."""
+    from paper_2208_12737_amd.plan import Item, objective_item
+    rng = np.random.default_rng(seed)
+    dets = [P.Detector(64, 64, 2.0, 2.0), P.Detector(37, 53, 1.7, 2.3, 3.0, -2.0),
+            P.Detector(20, 100, 0.9, 0.9)]
+    items = []
+    for k in range(n):
+        vi = int(rng.integers(0, 2))
+        det = dets[int(rng.integers(0, len(dets)))]
+        sdd = 1000.0 if vi == 0 else 300.0
+        pose = random_poses(1, math.pi / 8, 5.0, sdd, seed=500 * seed + k)[0]
+        pt = torch.from_numpy(pose).to(DEV)
+        if k % 3 == 2:
+            items.append(Item(vi, det, pt, torch.empty((det.height, det.width), device=DEV),
+                              torch.empty((det.height, det.width, 7), device=DEV)))
+            continue
+        gt = pt.clone()
+        gt[:3] += 0.03
+        target = P.render(vs[vi], gt[None], det)[0].contiguous()
+        img = torch.empty((det.height, det.width), device=DEV) if k % 2 == 0 else None
+        items.append(objective_item(vi, det, pt, target, image=img))
+    return items
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_plan_objective_items_match_fused_call(vols, use_graph, strategy):
+    """On the direct path's launch shape (16 x 16 px of 4 x 16 wave tiles) an
+    objective item's loss, gradient and image equal drr_render_ncc_grad's
+    bit for bit, whatever else is in the execute."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Plan
+    vs, _ = vols
+    plan = Plan(vs, max_items=32, use_graph=use_graph, strategy=strategy, tile_code=4)
+    for rep in range(3):
+        items = _objective_items(P, vs, seed=rep)
+        plan.execute(items)
+        torch.cuda.synchronize()
+        n_obj = 0
+        for it in items:
+            if it.target is None:
+                ref_i, ref_j = P.render(vs[it.volume], it.pose[None], it.det, jacobian=True)
+                assert torch.equal(it.image, ref_i[0])
+                continue
+            n_obj += 1
+            loss, grad, img = P.render_ncc_grad(vs[it.volume], it.pose[None], it.det, it.target,
+                                                return_image=True)
+            assert torch.isfinite(grad).all()
+            assert torch.equal(it.loss, loss), (it.loss, loss)
+            assert torch.equal(it.grad, grad[0]), (it.grad, grad)
+            if it.image is not None:
+                assert torch.equal(it.image, img[0])
+        assert n_obj >= 4
+    plan.close()
+
+
+@pytest.mark.parametrize("strategy", [0, 1])
+def test_plan_objective_items_other_shapes(vols, strategy):
+    """On the plan's default shape the tile sums are grouped differently, so
+    loss and gradient agree with the fused call to rounding; the gradient
+    is also checked against the oracle's Jacobian and ZNCC gradient."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Plan
+    vs, grids = vols
+    plan = Plan(vs, max_items=32, use_graph=True, strategy=strategy)
+    assert plan.config["tile_code"] != 4
+    items = _objective_items(P, vs, seed=11)
+    plan.execute(items)
+    torch.cuda.synchronize()
+    checked = 0
+    for it in items:
+        if it.target is None:
+            continue
+        loss, grad = P.render_ncc_grad(vs[it.volume], it.pose[None], it.det, it.target)
+        torch.testing.assert_close(it.loss, loss, rtol=0, atol=1e-6)
+        gscale = grad.abs().max().item()
+        torch.testing.assert_close(it.grad, grad[0], rtol=0, atol=1e-5 * gscale)
+        if checked < 2:
+            d = it.det
+            pose64 = it.pose.cpu().numpy().astype(np.float64)[None]
+            rimg, rjac = oracle.render_jacobian(grids[it.volume], pose64, d.height, d.width,
+                                                d.delta_x, d.delta_y,
+                                                offset=(d.offset_u, d.offset_v))
+            z, gz = oracle.zncc_grad(rimg[0], it.target.cpu().numpy().astype(np.float64))
+            ref_g = -np.einsum("hw,hwj->j", gz, rjac[0])
+            scale = np.abs(gz).sum() * np.abs(rjac[0]).max(axis=(0, 1))
+            assert abs(it.loss.item() + z) <= 1e-5
+            assert (np.abs(it.grad.cpu().numpy() - ref_g) / scale).max() <= 2e-4
+        checked += 1
+    assert checked >= 4
+    plan.close()
+
+
+def test_plan_rejects_bad_objective_items(vols):
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd import _lib
+    from paper_2208_12737_amd.plan import Item, Plan, objective_item
+    vs, _ = vols
+    plan = Plan(vs, max_items=4, use_graph=False)
+    det = P.Detector(8, 8, 1.0, 1.0)
+    pose = torch.zeros(7, device=DEV)
+    tgt = torch.ones((8, 8), device=DEV)
+    it = objective_item(0, det, pose, tgt)
+    bad = Item(0, det, pose, None, jac=torch.empty((8, 8, 7), device=DEV), target=tgt,
+               loss=it.loss, grad=it.grad, partials=it.partials)
+    with pytest.raises(_lib.DrrError):
+        plan.execute([bad])                           # JAC and NCC together
+    with pytest.raises(ValueError):
+        plan.execute([Item(0, det, pose, None, target=tgt, loss=it.loss, grad=it.grad)])
+    small = Item(0, det, pose, None, target=tgt, loss=it.loss, grad=it.grad,
+                 partials=it.partials[:1])
+    with pytest.raises(ValueError):
+        plan.execute([small])                         # scratch below the stated size
+    plan.close()
+
+
 def test_ct512_plan_in_the_benchmark_configuration(tmp_path):
     """The 256-pose clinical batch (512 x 512 x 133 CT, 256 x 256 detector at
     1.4 mm, SDD 1020 mm) through the plan with the shipped launch choice,
