@@ -59,11 +59,14 @@ __host__ __device__ constexpr int group_mode(int g)
 }
 
 struct PlanHeader {
-    int32_t first[kPlanModes];   // first item of each group
-    int32_t count[kPlanModes];   // items per group
-    int32_t tiles[kPlanModes];   // tiles per group
-    int32_t pad;
+    int32_t first[kPlanModes];     // first item of each group
+    int32_t count[kPlanModes];     // items per group
+    int32_t tiles[kPlanModes];     // tiles per group
+    int32_t uniform[kPlanModes];   // tiles per item when all items of the group
+                                   // have the same count, else 0
 };
+// the item table follows the header: keep its doubles aligned
+static_assert(sizeof(PlanHeader) % 16 == 0, "PlanHeader size must keep items aligned");
 
 struct Slot {
     PlanHeader* h_header = nullptr;   // pinned: header followed by items
@@ -80,6 +83,23 @@ struct Slot {
 __global__ void k_reset_counters(int32_t* c, int n)
 {
     if ((int)threadIdx.x < n) c[threadIdx.x] = 0;
+}
+
+// Item of tile t within group g: a division when all items of the group have
+// the same tile count, else a binary search for the last item whose first
+// tile is <= t.  Every operand is wave-uniform.
+__device__ inline int item_of_tile(const PlanHeader* hdr, const PlanItem* items, int g, int t)
+{
+    const int u = hdr->uniform[g];
+    if (u > 0) return t / u;
+    const int first = hdr->first[g];
+    int lo = 0, hi = hdr->count[g] - 1;
+    while (lo < hi) {
+        const int mid = (lo + hi + 1) >> 1;
+        if (items[first + mid].tile_begin <= t) lo = mid;
+        else hi = mid - 1;
+    }
+    return lo;
 }
 
 // Next tile of group `g` for a workgroup on XCD `xcd`, or -1 when drained.
@@ -105,7 +125,7 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
     __shared__ double lds[MODE == kNcc ? kNccSums * WX * WY : 1];
     const PlanHeader* hdr = (const PlanHeader*)block;
     const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
-    const int first = hdr->first[group], count = hdr->count[group], total = hdr->tiles[group];
+    const int first = hdr->first[group], total = hdr->tiles[group];
     int32_t* ctr = counters + group * kXcds;
     const int xcd = (int)(blockIdx.x % kXcds);
     int scan = 0;
@@ -117,14 +137,7 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
         const int t = __builtin_amdgcn_readfirstlane(s_tile);
         __syncthreads();
         if (t < 0) break;
-        // binary search: last item with tile_begin <= t
-        int lo = 0, hi = count - 1;
-        while (lo < hi) {
-            const int mid = (lo + hi + 1) >> 1;
-            if (items[first + mid].tile_begin <= t) lo = mid;
-            else hi = mid - 1;
-        }
-        const PlanItem& it = items[first + lo];
+        const PlanItem& it = items[first + item_of_tile(hdr, items, group, t)];
         const int local = t - it.tile_begin;
         const int ty = local / it.tiles_x, tx = local % it.tiles_x;
         TileOut o;
@@ -148,15 +161,8 @@ __global__ __launch_bounds__(64 * WX * WY) void render_plan_flat(const char* __r
     __shared__ double lds[MODE == kNcc ? kNccSums * WX * WY : 1];
     const PlanHeader* hdr = (const PlanHeader*)block;
     const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
-    const int first = hdr->first[group], count = hdr->count[group];
     const int t = (int)xcd_logical(blockIdx.x, gridDim.x);
-    int lo = 0, hi = count - 1;
-    while (lo < hi) {
-        const int mid = (lo + hi + 1) >> 1;
-        if (items[first + mid].tile_begin <= t) lo = mid;
-        else hi = mid - 1;
-    }
-    const PlanItem& it = items[first + lo];
+    const PlanItem& it = items[hdr->first[group] + item_of_tile(hdr, items, group, t)];
     const int local = t - it.tile_begin;
     const int ty = local / it.tiles_x, tx = local % it.tiles_x;
     TileOut o;
@@ -338,7 +344,8 @@ static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int
     for (int m = 0; m < kPlanModes; ++m) {
         h->first[m] = pos;
         h->count[m] = 0;
-        int64_t tiles = 0;
+        h->uniform[m] = 0;
+        int64_t tiles = 0, per = -1;
         for (int i = 0; i < n; ++i) {
             const drr_work_item& w = items[i];
             if (group_of_flags(w.flags) != m) continue;
@@ -357,8 +364,10 @@ static int32_t stage_items(drr_plan* p, Slot& s, const drr_work_item* items, int
             it.tiles = (int32_t)t;
             it.tile_begin = (int32_t)tiles;
             tiles += t;
+            per = per == -1 || per == t ? t : 0;
             h->count[m]++;
         }
+        if (per > 0 && per <= 0x7FFFFFFF) h->uniform[m] = (int32_t)per;
         if (tiles > 0x7FFFFFFF) return fail(DRR_ENOTSUP, "too many tiles in one execute");
         h->tiles[m] = (int32_t)tiles;
         if (tiles > 0) *mask |= 1 << m;

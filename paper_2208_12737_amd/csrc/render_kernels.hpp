@@ -81,10 +81,13 @@ __device__ inline void block_sums(double (&vals)[NS], double* lds, double* out)
     __syncthreads();
 }
 
+// Always inlined: an out-of-line call (the plan kernels have two call sites
+// per instance) passes the volume and detector fields in vector registers and
+// turns their uses into per-lane loads.
 template <int TW, int WX, int WY, int MODE>
-__device__ inline void render_tile(const VolArgs& V, const DetArgs& D,
-                                   const float* __restrict__ pose, int tx, int ty,
-                                   const TileOut& o, double* lds)
+__device__ __forceinline__ void render_tile(const VolArgs& V, const DetArgs& D,
+                                            const float* __restrict__ pose, int tx, int ty,
+                                            const TileOut& o, double* lds)
 {
     using S = TileShape<TW, WX, WY>;
     using T = ModeTraits<MODE>;
