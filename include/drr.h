@@ -269,29 +269,38 @@ typedef struct drr_plan_desc {
     int32_t use_graph;                   /* 1: capture the launch in a HIP graph */
     int32_t autotune;                    /* 1: time candidate launch shapes at create */
     const char* tune_cache_path;         /* NULL or a file for autotune results */
-    int32_t strategy;                    /* without autotune: DRR_PLAN_* (-1 = default) */
-    int32_t tile_code;                   /* without autotune: launch shape (-1 = default) */
-    int32_t wg_per_cu;                   /* without autotune: workgroups per CU (0 = max) */
+    int32_t strategy;                    /* without autotune: DRR_PLAN_* (-1 = default:
+                                            DRR_PLAN_AUTO) */
+    int32_t tile_code;                   /* without autotune: launch shape (-1 = default: 4,
+                                            16 x 16-pixel tiles of 4 x 16-pixel waves) */
+    int32_t wg_per_cu;                   /* without autotune: resident workgroups per CU
+                                            (-1 = default: 4; 0 = as many as registers
+                                            allow) */
 } drr_plan_desc;
 
 /* Plan strategies: a persistent grid sized to the GPU whose workgroups pull
  * tiles from per-XCD device queues (one graph serves any batch), or one
  * workgroup per tile (the graph is re-captured when the tile count of a
- * batch changes). */
+ * batch changes), or, per output group of each execute, the flat grid when
+ * the group has no more tiles than the persistent grid has workgroups and
+ * the queues otherwise (small batches start sooner; large ones keep the
+ * queues' balance under concurrent executes). */
 #define DRR_PLAN_PERSISTENT 0
 #define DRR_PLAN_FLAT 1
+#define DRR_PLAN_AUTO 2
 
 typedef struct drr_plan drr_plan;
 
-/* Creates a plan (allocates its device item table and, when autotuning,
- * runs timed candidates on `stream` using tune_items as the sample work;
- * tune_items may be NULL to tune on a built-in synthetic sample). */
+/* Creates a plan (allocates its device item tables and, when autotuning,
+ * runs timed candidates of the persistent and flat strategies on `stream`
+ * using tune_items, at least one item, as the sample work; without
+ * autotuning tune_items is ignored and may be NULL). */
 int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_items,
                         int32_t n_tune_items, void* stream, drr_plan** out);
 
 /* Enqueues the items on `stream`.  Items are independent; their results are
  * identical to rendering each alone.  The host table is copied before the
- * call returns.  A plan is not thread-safe: one execute at a time per plan. */
+ * call returns.  Calls on one plan are serialized by a lock inside it. */
 int32_t drr_plan_execute(drr_plan* plan, const drr_work_item* items, int32_t n_items,
                          void* stream);
 

@@ -24,6 +24,7 @@ DRR_ITEM_COUNT = 2
 DRR_ITEM_NCC = 4
 DRR_PLAN_PERSISTENT = 0
 DRR_PLAN_FLAT = 1
+DRR_PLAN_AUTO = 2
 
 
 class DrrError(RuntimeError):

@@ -262,7 +262,7 @@ static FlatFn flat_kernel_for(int group, int code)
     }
 }
 
-enum Strategy { kPersistent = 0, kFlat = 1 };
+enum Strategy { kPersistent = 0, kFlat = 1, kAuto = 2 };
 
 // Group of an item: 0 image, 1 image + counts, 2 image + Jacobian,
 // 3 objective.
@@ -299,7 +299,7 @@ struct drr_plan {
     int max_items = 0;
     std::vector<drr_volume_desc> vols;
     std::vector<const void*> packed;
-    int strategy = 0;          // kPersistent or kFlat
+    int strategy = 0;          // kPersistent, kFlat or kAuto
     int tile_code = 0;
     int wg_per_cu = 0;         // requested workgroups per CU (0 = occupancy limit)
     int grid[kPlanModes] = {0, 0, 0, 0};   // persistent grid per group
@@ -385,26 +385,34 @@ static int32_t enqueue_finalize(Slot& s, int mask, hipStream_t st)
     return check_launch("plan objective finalize");
 }
 
+// Strategy of group m in the staged execute.
+static int group_strategy(const drr_plan* p, const Slot& s, int m)
+{
+    if (p->strategy != kAuto) return p->strategy;
+    return s.h_header->tiles[m] <= p->grid[m] ? kFlat : kPersistent;
+}
+
 static int32_t enqueue_kernels(drr_plan* p, Slot& s, int mask, hipStream_t st)
 {
     const ShapeInfo& sh = kShapes[p->tile_code];
     const int threads = 64 * sh.wx * sh.wy;
     int32_t rc;
-    if (p->strategy == kFlat) {
-        for (int m = 0; m < kPlanModes; ++m) {
-            if (!(mask & (1 << m))) continue;
+    bool counters_reset = false;
+    for (int m = 0; m < kPlanModes; ++m) {
+        if (!(mask & (1 << m))) continue;
+        if (group_strategy(p, s, m) == kFlat) {
             const size_t lds = occupancy_lds(p->wg_per_cu, plan_static_lds(m, sh));
             hipLaunchKernelGGL(flat_kernel_for(m, p->tile_code), dim3(s.h_header->tiles[m]),
                                dim3(threads), lds, st, (const char*)s.d_block, m);
             if ((rc = check_launch("plan flat kernel"))) return rc;
+            continue;
         }
-        return enqueue_finalize(s, mask, st);
-    }
-    hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, s.d_counters,
-                       kPlanModes * kXcds);
-    if ((rc = check_launch("plan counter reset"))) return rc;
-    for (int m = 0; m < kPlanModes; ++m) {
-        if (!(mask & (1 << m))) continue;
+        if (!counters_reset) {
+            hipLaunchKernelGGL(k_reset_counters, dim3(1), dim3(64), 0, st, s.d_counters,
+                               kPlanModes * kXcds);
+            if ((rc = check_launch("plan counter reset"))) return rc;
+            counters_reset = true;
+        }
         hipLaunchKernelGGL(kernel_for(m, p->tile_code), dim3(p->grid[m]), dim3(threads), 0, st,
                            (const char*)s.d_block, s.d_counters, m);
         if ((rc = check_launch("plan persistent kernel"))) return rc;
@@ -433,9 +441,14 @@ static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hi
     hipError_t e = hipMemcpyAsync(s.d_block, s.h_header, bytes, hipMemcpyHostToDevice, st);
     if (e != hipSuccess) return fail(DRR_EHIP, "plan table copy: %s", hipGetErrorString(e));
     if (p->use_graph && st != nullptr) {
+        // what the captured launches depend on: groups present, the
+        // finalize grid, and each group's strategy with its flat grid size
         std::vector<int> key = {mask, s.h_header->count[3]};
-        if (p->strategy == kFlat)
-            for (int m = 0; m < kPlanModes; ++m) key.push_back(s.h_header->tiles[m]);
+        for (int m = 0; m < kPlanModes; ++m) {
+            const int g = group_strategy(p, s, m);
+            key.push_back(g);
+            key.push_back(g == kFlat ? s.h_header->tiles[m] : 0);
+        }
         auto found = s.graphs.find(key);
         if (found == s.graphs.end()) {
             hipGraph_t g = nullptr;
@@ -680,13 +693,16 @@ int32_t drr_plan_create(const drr_plan_desc* desc, const drr_work_item* tune_ite
             free_plan(p);
             return fail(DRR_EINVAL, "plan_create: tile_code must be < %d", kNumShapes);
         }
-        if (desc->strategy > kFlat) {
+        if (desc->strategy > kAuto) {
             free_plan(p);
             return fail(DRR_EINVAL, "plan_create: unknown strategy %d", desc->strategy);
         }
-        p->strategy = desc->strategy >= 0 ? desc->strategy : kFlat;
-        p->tile_code = desc->tile_code >= 0 ? desc->tile_code : 2;
-        p->wg_per_cu = desc->wg_per_cu > 0 ? desc->wg_per_cu : 0;
+        // defaults: the launch shape the autotuner picks for the 512 x 512 x
+        // 133 CT with 256 x 256 detectors (4 workgroups per CU keep the
+        // gather working set in cache), and the strategy chosen per execute
+        p->strategy = desc->strategy >= 0 ? desc->strategy : kAuto;
+        p->tile_code = desc->tile_code >= 0 ? desc->tile_code : 4;
+        p->wg_per_cu = desc->wg_per_cu >= 0 ? desc->wg_per_cu : 4;
     }
     int32_t rc = compute_grids(p);
     if (rc == DRR_OK && desc->autotune) {

@@ -113,7 +113,7 @@ class Plan:
     def __init__(self, volumes: Sequence[Volume], max_items: int = 1024, use_graph: bool = True,
                  autotune: bool = False, tune_items: Optional[Sequence[Item]] = None,
                  cache_path: Optional[str] = None, strategy: int = -1, tile_code: int = -1,
-                 wg_per_cu: int = 0):
+                 wg_per_cu: int = -1):
         self.volumes = list(volumes)
         self._descs = (_lib.VolumeDesc * len(self.volumes))(*[v.desc for v in self.volumes])
         self._packed = (ctypes.c_void_p * len(self.volumes))(
@@ -149,7 +149,9 @@ class Plan:
         s, t, w, g = ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32(), ctypes.c_int32()
         _lib.call("drr_plan_config", self._h, ctypes.byref(s), ctypes.byref(t), ctypes.byref(w),
                   ctypes.byref(g))
-        return {"strategy": "flat" if s.value == _lib.DRR_PLAN_FLAT else "persistent",
+        names = {_lib.DRR_PLAN_PERSISTENT: "persistent", _lib.DRR_PLAN_FLAT: "flat",
+                 _lib.DRR_PLAN_AUTO: "auto"}
+        return {"strategy": names[s.value],
                 "tile_code": t.value, "wg_per_cu": w.value, "use_graph": bool(g.value)}
 
     def close(self):

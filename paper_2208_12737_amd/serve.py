@@ -8,9 +8,10 @@ arrive at any time.  Each scheduler tick
      stays within the HBM budget and a slot is free (a request larger than
      the whole budget is rejected at submission),
   3. launches the admitted requests as one batch on the next of a few
-     streams: all forward requests in one persistent plan launch (any mix of
-     volumes and detector sizes), forward + backward requests as one fused
-     render + NCC + pose-gradient launch per (volume, detector) group.
+     streams: one plan execute renders every request (any mix of volumes
+     and detector sizes); forward + backward requests are objective items of
+     that execute, which also reduce -ZNCC against their target and its pose
+     gradient.
 Batches on different streams overlap on the device, so requests that arrive
 while others run are admitted as soon as memory and slots free up.  Every
 result is computed by the same per-ray and per-pose kernels as a request
@@ -24,6 +25,7 @@ object (``GpuBackend`` here, or a stand-in in tests).
 from __future__ import annotations
 
 import collections
+import ctypes
 import threading
 import time
 from dataclasses import dataclass, field
@@ -203,10 +205,13 @@ class Server:
 # ---------------------------------------------------------------- GPU backend
 
 class GpuBackend:
-    """Runs batches on the GPU through libdrr (plans and the fused NCC call)."""
+    """Runs each batch as one execute of a plan over the resident volumes.
 
-    def __init__(self, volumes: Dict[str, Any], n_streams: int = 2, max_items: int = 2048,
-                 autotune_items=None):
+    The work-item table is filled here directly from the requests (the
+    buffers are allocated here, so the per-item checks of ``Plan.execute``
+    are not repeated); the library still validates every item."""
+
+    def __init__(self, volumes: Dict[str, Any], n_streams: int = 2, max_items: int = 2048):
         import torch
         from .plan import Plan
         self.torch = torch
@@ -215,58 +220,92 @@ class GpuBackend:
         self.index = {n: i for i, n in enumerate(self.names)}
         self.streams = [torch.cuda.Stream() for _ in range(n_streams)]
         self.plan = Plan([volumes[n] for n in self.names], max_items=max_items, use_graph=False)
-        self.dev = volumes[self.names[0]].device
+        self.dev = volumes[self.names[0]].packed.device
+        self._dets: Dict[tuple, tuple] = {}   # (H, W, dx, dy) -> (desc, scratch doubles)
+
+    def _det(self, r: Request):
+        key = (r.height, r.width, r.delta_x, r.delta_y)
+        d = self._dets.get(key)
+        if d is None:
+            from . import _lib
+            desc = _lib.detector_desc(r.height, r.width, r.delta_x, r.delta_y)
+            ws = int(_lib.load().drr_plan_item_workspace_bytes(ctypes.byref(desc)))
+            if ws == 0:
+                raise ValueError(f"invalid detector {key}")
+            d = self._dets[key] = (desc, ws // 8)
+        return d
 
     def bytes_for(self, req: Request) -> int:
-        from .drr import Detector
-        from .plan import item_workspace_bytes
-        px = req.height * req.width * 4
+        if req.volume not in self.index:
+            raise KeyError(f"unknown volume {req.volume!r}")
+        _, ws = self._det(req)
+        px = req.height * req.width
         if req.kind == FWD:
-            return px + 64
-        det = Detector(req.height, req.width, req.delta_x, req.delta_y)
-        return px + item_workspace_bytes(det) + 32 + 64
+            return 4 * px + 64
+        t = req.target
+        torch = self.torch
+        if not (isinstance(t, torch.Tensor) and t.device == self.dev and
+                t.dtype == torch.float32 and t.is_contiguous() and t.numel() == px):
+            raise ValueError("target must be a contiguous float32 tensor of height x width "
+                             "pixels on the volumes' device")
+        return 4 * px + 8 * ws + 32 + 64
 
     def launch(self, tickets: List[Ticket], stream_idx: int):
         """One plan execute for the whole batch: forward items render an
         image, fwd+bwd items also reduce -ZNCC against their target and its
         pose gradient in the same launch."""
         torch = self.torch
-        from .drr import Detector
-        from .plan import objective_item, Item
+        from . import _lib
         stream = self.streams[stream_idx]
         stream.wait_stream(torch.cuda.current_stream())
         n = len(tickets)
+        reqs = [t.request for t in tickets]
         host = torch.empty((n, 7), dtype=torch.float32, pin_memory=True)
-        host.numpy()[:] = np.stack([np.asarray(t.request.pose, np.float32) for t in tickets])
-        out = {}
-        keep = []
+        host.numpy()[:] = np.stack([np.asarray(r.pose, np.float32) for r in reqs])
+        dets = [self._det(r) for r in reqs]
+        obj = [k for k, r in enumerate(reqs) if r.kind != FWD]
+        out = [None] * n
+        arr = (_lib.WorkItem * n)()
         with torch.cuda.stream(stream):
             poses = host.to(self.dev, non_blocking=True)
-            items = []
-            for k, t in enumerate(tickets):
-                r = t.request
-                det = Detector(r.height, r.width, r.delta_x, r.delta_y)
+            lg = parts = None
+            if obj:
+                # loss and gradient of objective item j at lg[j, 0] and lg[j, 1:8]
+                lg = torch.empty((len(obj), 8), dtype=torch.float32, device=self.dev)
+                parts = torch.empty(sum(dets[k][1] for k in obj), dtype=torch.float64,
+                                    device=self.dev)
+            pbase = poses.data_ptr()
+            j = poff = 0
+            for k, r in enumerate(reqs):
                 img = torch.empty((r.height, r.width), dtype=torch.float32, device=self.dev)
+                w = arr[k]
+                w.volume = self.index[r.volume]
+                w.det = dets[k][0]
+                w.pose = pbase + 28 * k
+                w.image = img.data_ptr()
                 if r.kind == FWD:
-                    items.append(Item(self.index[r.volume], det, poses[k], img))
                     out[k] = img
-                else:
-                    tg = r.target.reshape(r.height, r.width).contiguous()
-                    it = objective_item(self.index[r.volume], det, poses[k], tg, image=img)
-                    items.append(it)
-                    keep.append(tg)
-                    out[k] = (img, it.loss[0], it.grad)
-            self.plan.execute(items)
+                    continue
+                w.flags = _lib.DRR_ITEM_NCC
+                w.target = r.target.data_ptr()
+                w.loss = lg.data_ptr() + 32 * j
+                w.grad = w.loss + 4
+                w.partials = parts.data_ptr() + 8 * poff
+                out[k] = (img, lg[j, 0], lg[j, 1:])
+                j += 1
+                poff += dets[k][1]
+            _lib.call("drr_plan_execute", self.plan._h, arr, n, stream.cuda_stream)
             ev = torch.cuda.Event()
             ev.record(stream)
-        return (ev, out, n, (host, keep, items))
+        # the host pose buffer, the pose copy and the scratch stay referenced
+        # until the batch completes
+        return (ev, out, (host, poses, parts, reqs))
 
     def poll(self, h) -> bool:
         return h[0].query()
 
     def collect(self, h):
-        ev, out, n, _ = h
-        return [out[k] for k in range(n)]
+        return h[1]
 
 
 def plain_forward(volumes: Dict[str, Any], req: Request):

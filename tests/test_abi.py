@@ -138,3 +138,17 @@ def test_work_item_layout_matches_header():
     assert W.pose.offset == 8 + ctypes.sizeof(_lib.DetectorDesc)
     assert W.partials.offset == W.pose.offset + 7 * 8
     assert ctypes.sizeof(W) == W.partials.offset + 8
+
+
+def test_packed_copy_size_limit():
+    """Gathers address one zero-bordered copy with 32-bit byte offsets: a
+    copy must stay below 4 GiB; the per-axis layout holds three copies."""
+    lib = _lib.load()
+    ok = _lib.volume_desc((1021, 1021, 1021), (1, 1, 1), (0, 0, 0))
+    assert lib.drr_volume_packed_bytes(ctypes.byref(ok)) == 1023 ** 3 * 4
+    ok3 = _lib.volume_desc((1021, 1021, 1021), (1, 1, 1), (0, 0, 0), _lib.DRR_LAYOUT_PER_AXIS)
+    assert lib.drr_volume_packed_bytes(ctypes.byref(ok3)) == 3 * 1023 ** 3 * 4
+    big = _lib.volume_desc((1022, 1022, 1022), (1, 1, 1), (0, 0, 0))
+    assert lib.drr_volume_packed_bytes(ctypes.byref(big)) == 0
+    assert lib.drr_volume_pack(None, None, ctypes.byref(big), None) == _lib.DRR_ENOTSUP
+    assert b"4 GiB" in lib.drr_last_error()

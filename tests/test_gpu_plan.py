@@ -53,7 +53,7 @@ def _mixed_items(P, vols, seed):
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("strategy", [0, 1, 2])
 def test_plan_matches_plain_render(vols, use_graph, strategy):
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.plan import Plan
@@ -81,7 +81,35 @@ def test_plan_matches_plain_render(vols, use_graph, strategy):
     plan.close()
 
 
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("code", range(9))
+def test_every_launch_shape(vols, code):
+    """Each of the nine launch shapes (wave tile width x waves per
+    workgroup), under both strategies and occupancy limits, renders what
+    the plain per-call path renders."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Plan
+    vs, _ = vols
+    plan = Plan(vs, max_items=64, use_graph=False, strategy=code % 2, tile_code=code,
+                wg_per_cu=0 if code % 3 == 0 else 4)
+    assert plan.config["tile_code"] == code
+    items = _mixed_items(P, vs, seed=20 + code)
+    plan.execute(items)
+    torch.cuda.synchronize()
+    for it in items:
+        if it.jac is not None:
+            ref_i, ref_j = P.render(vs[it.volume], it.pose[None], it.det, jacobian=True)
+            torch.testing.assert_close(it.jac, ref_j[0], rtol=1e-6,
+                                       atol=1e-6 * ref_j.abs().max().item())
+        elif it.counts is not None:
+            ref_i, ref_c = P.render_count(vs[it.volume], it.pose[None], it.det)
+            assert torch.equal(it.counts, ref_c[0])
+        else:
+            ref_i = P.render(vs[it.volume], it.pose[None], it.det)
+        torch.testing.assert_close(it.image, ref_i[0], rtol=1e-6, atol=1e-6)
+    plan.close()
+
+
+@pytest.mark.parametrize("strategy", [0, 1, 2])
 def test_plan_is_deterministic(vols, strategy):
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.plan import Plan
@@ -136,9 +164,10 @@ def test_plan_rejects_bad_items(vols):
     plan.close()
 
 
-def _objective_items(P, vs, seed, n=10):
+def _objective_items(P, vs, seed, n=10, same_det=False):
     """Objective items mixed with image and Jacobian items; targets are DRRs
-    at perturbed poses."""
+    at perturbed poses.  same_det: one detector for all (each group then
+    finds its items by division rather than by search)."""
     from paper_2208_12737_amd.plan import Item, objective_item
     rng = np.random.default_rng(seed)
     dets = [P.Detector(64, 64, 2.0, 2.0), P.Detector(37, 53, 1.7, 2.3, 3.0, -2.0),
@@ -146,7 +175,7 @@ def _objective_items(P, vs, seed, n=10):
     items = []
     for k in range(n):
         vi = int(rng.integers(0, 2))
-        det = dets[int(rng.integers(0, len(dets)))]
+        det = dets[0 if same_det else int(rng.integers(0, len(dets)))]
         sdd = 1000.0 if vi == 0 else 300.0
         pose = random_poses(1, math.pi / 8, 5.0, sdd, seed=500 * seed + k)[0]
         pt = torch.from_numpy(pose).to(DEV)
@@ -163,7 +192,7 @@ def _objective_items(P, vs, seed, n=10):
 
 
 @pytest.mark.parametrize("use_graph", [False, True])
-@pytest.mark.parametrize("strategy", [0, 1])
+@pytest.mark.parametrize("strategy", [0, 1, 2])
 def test_plan_objective_items_match_fused_call(vols, use_graph, strategy):
     """On the direct path's launch shape (16 x 16 px of 4 x 16 wave tiles) an
     objective item's loss, gradient and image equal drr_render_ncc_grad's
@@ -172,8 +201,8 @@ def test_plan_objective_items_match_fused_call(vols, use_graph, strategy):
     from paper_2208_12737_amd.plan import Plan
     vs, _ = vols
     plan = Plan(vs, max_items=32, use_graph=use_graph, strategy=strategy, tile_code=4)
-    for rep in range(3):
-        items = _objective_items(P, vs, seed=rep)
+    for rep in range(4):
+        items = _objective_items(P, vs, seed=rep, same_det=rep == 3)
         plan.execute(items)
         torch.cuda.synchronize()
         n_obj = 0
@@ -196,14 +225,15 @@ def test_plan_objective_items_match_fused_call(vols, use_graph, strategy):
 
 @pytest.mark.parametrize("strategy", [0, 1])
 def test_plan_objective_items_other_shapes(vols, strategy):
-    """On the plan's default shape the tile sums are grouped differently, so
-    loss and gradient agree with the fused call to rounding; the gradient
-    is also checked against the oracle's Jacobian and ZNCC gradient."""
+    """On another launch shape (8 x 32-pixel tiles) the tile sums are grouped
+    differently, so loss and gradient agree with the fused call to rounding;
+    the gradient is also checked against the oracle's Jacobian and ZNCC
+    gradient."""
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.plan import Plan
     vs, grids = vols
-    plan = Plan(vs, max_items=32, use_graph=True, strategy=strategy)
-    assert plan.config["tile_code"] != 4
+    plan = Plan(vs, max_items=32, use_graph=True, strategy=strategy, tile_code=2)
+    assert plan.config["tile_code"] == 2
     items = _objective_items(P, vs, seed=11)
     plan.execute(items)
     torch.cuda.synchronize()
@@ -228,6 +258,44 @@ def test_plan_objective_items_other_shapes(vols, strategy):
             assert (np.abs(it.grad.cpu().numpy() - ref_g) / scale).max() <= 2e-4
         checked += 1
     assert checked >= 4
+    plan.close()
+
+
+@pytest.mark.parametrize("use_graph", [False, True])
+def test_auto_strategy_mixes_flat_and_persistent_groups(vols, use_graph):
+    """Default strategy: a group with more tiles than the persistent grid
+    holds (24 images of 256 x 256 pixels, 6144 tiles) goes through the
+    queues, a small one (objective items) through the flat grid, in one
+    execute; the composition changes between replays."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Item, Plan, objective_item
+    vs, _ = vols
+    plan = Plan(vs, max_items=64, use_graph=use_graph)
+    assert plan.config["strategy"] == "auto" and plan.config["tile_code"] == 4
+    big = P.Detector(256, 256, 0.5, 0.5)
+    small = P.Detector(48, 40, 2.0, 2.0)
+    for rep, n_big in enumerate((24, 2, 24)):
+        poses = torch.from_numpy(random_poses(n_big + 3, math.pi / 8, 5.0, 1000.0,
+                                              seed=40 + rep)).to(DEV)
+        items = [Item(0, big, poses[k], torch.empty((256, 256), device=DEV))
+                 for k in range(n_big)]
+        for k in range(n_big, n_big + 3):
+            gt = poses[k].clone()
+            gt[:3] += 0.03
+            target = P.render(vs[0], gt[None], small)[0].contiguous()
+            items.append(objective_item(0, small, poses[k], target,
+                                        image=torch.empty((48, 40), device=DEV)))
+        plan.execute(items)
+        torch.cuda.synchronize()
+        for it in items:
+            if it.target is None:
+                ref = P.render(vs[0], it.pose[None], it.det)
+                assert torch.equal(it.image, ref[0])
+            else:
+                loss, grad, img = P.render_ncc_grad(vs[0], it.pose[None], it.det, it.target,
+                                                    return_image=True)
+                assert torch.equal(it.image, img[0])
+                assert torch.equal(it.loss, loss) and torch.equal(it.grad, grad[0])
     plan.close()
 
 

@@ -219,6 +219,37 @@ def test_ct512_full_image_one_pose(ct512):
     assert d.max() <= 1 and (d == 0).mean() > 0.999
 
 
+def test_largest_serving_volume_and_detector():
+    """The largest volume of the serving mix (512 x 512 x 300 at 0.7 x 0.7 x
+    1.25 mm, 315 MB, three per-axis copies) with its largest detector
+    (512 x 512 at 0.7 mm): sampled pixels of a 16-pose batch against the
+    oracle, and one pose alone equal to the same pose in the batch."""
+    P = _lib_objs()
+    ph = make_phantom("ct512x300", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    poses = random_poses(16, math.pi / 6, 30.0, 1020.0, seed=4)
+    det = P.Detector(512, 512, 0.7, 0.7)
+    img = P.render(vol, _gpu(poses), det).cpu().numpy()
+    rng = np.random.default_rng(5)
+    src, dst, got = [], [], []
+    for b in rng.choice(16, 6, replace=False):
+        for _ in range(40):
+            h, w = int(rng.integers(0, 512)), int(rng.integers(0, 512))
+            s, p = oracle.ray_endpoints(poses[b].astype(np.float64), 512, 512, 0.7, 0.7, h, w)
+            src.append(s)
+            dst.append(p)
+            got.append(img[b, h, w])
+    ref, _, _ = oracle.trace_rays(grid, np.array(src), np.array(dst), nthreads=4)
+    assert (ref > 0).mean() > 0.5          # most sampled rays cross the body
+    rel, small = image_errors(np.array(got), ref)
+    assert rel <= 1e-5 and small <= 1e-5, (rel, small)
+    alone = P.render(vol, _gpu(poses[9:10]), det).cpu().numpy()
+    np.testing.assert_array_equal(alone[0], img[9])
+    del vol
+    torch.cuda.empty_cache()
+
+
 def test_layouts_render_identically(small, ct512):
     """The per-axis copies only change memory order: renders, counts and
     Jacobians are bitwise equal to the single-copy layout, for poses whose

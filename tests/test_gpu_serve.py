@@ -84,3 +84,19 @@ def test_alone_vs_mix_and_plain(volumes):
         else:
             img, loss, grad = mixed
             assert torch.isfinite(grad).all() and loss.item() < 0
+
+
+def test_bad_requests_fail_at_submission(volumes):
+    from paper_2208_12737_amd.serve import FWD, FWDBWD, GpuBackend, Request, Server
+    srv = Server(GpuBackend(volumes, n_streams=1), hbm_budget_bytes=1 << 30)
+    pose = np.zeros(7, np.float32)
+    pose[6] = 400.0
+    with pytest.raises(KeyError):
+        srv.submit(Request("missing", 8, 8, 1.0, 1.0, pose, FWD))
+    with pytest.raises(ValueError):       # target of the wrong size
+        srv.submit(Request("a", 8, 8, 1.0, 1.0, pose, FWDBWD, torch.zeros(9, device=DEV)))
+    with pytest.raises(ValueError):       # target on the host
+        srv.submit(Request("a", 8, 8, 1.0, 1.0, pose, FWDBWD, torch.zeros(64)))
+    with pytest.raises(ValueError):       # invalid detector
+        srv.submit(Request("a", 0, 8, 1.0, 1.0, pose, FWD))
+    assert srv.pending() == 0
