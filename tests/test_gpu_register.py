@@ -52,6 +52,27 @@ def test_graph_replays_equal_eager():
         del junk
 
 
+@pytest.mark.parametrize("chains", [2, 3])
+def test_chains_give_identical_results(chains):
+    """Problems split over independent streams (graph branches) follow
+    exactly the trajectories of the single chain, eager and replayed."""
+    from paper_2208_12737_amd.register import BatchedRegistration, default_rates
+    vol, det, gt, targets, init = _problem(n=5, seed=7)
+    rates = default_rates(5, rot=2e-2, xyz=20.0)
+    one = BatchedRegistration(vol, det, targets, init, rates, steps=12, use_graph=False,
+                              chains=1)
+    p1, h1 = one.run()
+    p1, h1 = p1.clone(), h1.clone()
+    for use_graph in (False, True):
+        reg = BatchedRegistration(vol, det, targets, init, rates, steps=12, use_graph=use_graph,
+                                  chains=chains)
+        for rep in range(2):
+            pc, hc = reg.run()
+            torch.cuda.synchronize()
+            assert torch.equal(pc, p1), (use_graph, rep)
+            assert torch.equal(hc, h1), (use_graph, rep)
+
+
 def test_loss_decreases():
     from paper_2208_12737_amd.register import BatchedRegistration, default_rates
     vol, det, gt, targets, init = _problem(seed=3)
