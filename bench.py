@@ -382,12 +382,26 @@ def bench_landscape(args):
     loss = sweep(vol, det, gt, off, chunk=8192)
     torch.cuda.synchronize()
     dt = time.perf_counter() - t0
+    # gathers per pose of this box, counted on the first 2048 offsets
+    ns = 2048
+    cnt = 0
+    gt_t = torch.from_numpy(np.asarray(gt, np.float32).reshape(1, 7)).cuda()
+    off_t = torch.from_numpy(off[:ns]).cuda()
+    for s0 in range(0, ns, 512):
+        _, c = P.render_count(vol, (gt_t + off_t[s0:s0 + 512]).contiguous(), det)
+        cnt += int(c.to(torch.int64).sum().item())
+    per_pose = cnt / ns
+    bytes_per_pose = 4 * per_pose + 4 * det.pixels      # gathers + target read
     g1 = sweep(vol, det, gt, grid_offsets(0, 1, math.radians(90), math.radians(90), 129))
     g2 = sweep(vol, det, gt, grid_offsets(3, 4, 30.0, 30.0, 129))
     frac, _ = radial_monotonicity(vol, det, gt, n_dirs=256, n_steps=16, radius=0.25)
     res = {"metric": "loss-landscape poses/s (render + -ZNCC per pose)", "mode": "landscape",
            "poses": n, "detector": [256, 256], "volume": [512, 512, 133],
            "poses_per_s": n / dt, "wall_s": dt,
+           "gathers_per_pose_sampled": per_pose,
+           "gvox_gathers_per_s": n / dt * per_pose / 1e9,
+           "algorithmic_GBps": n / dt * bytes_per_pose / 1e9,
+           "hbm_roofline_frac": n / dt * bytes_per_pose / 8.0e12,
            "loss_quantiles": [float(q) for q in np.quantile(loss, [0, 0.01, 0.5, 0.99, 1])],
            "grid_theta_phi": {"argmin_at_centre": bool(np.argmin(g1) == 129 * 64 + 64),
                               "min": float(g1.min())},

@@ -33,6 +33,7 @@ namespace drr {
 constexpr int kPlanModes = 4;   // groups: kImage, kCount, kJac, kNcc (see group_mode)
 constexpr int kXcds = 8;
 constexpr int kRing = 4;        // item tables in flight
+constexpr size_t kMaxGraphsPerSlot = 16;   // captured launches kept per item table
 constexpr int kMaxPlanItems = 8192;
 
 struct PlanItem {
@@ -451,6 +452,10 @@ static int32_t execute_locked(drr_plan* p, const drr_work_item* items, int n, hi
         }
         auto found = s.graphs.find(key);
         if (found == s.graphs.end()) {
+            // bound the cache: batches of ever new shapes would otherwise
+            // keep one executable graph each (this slot's last launch has
+            // completed, so its graphs are idle)
+            if (s.graphs.size() >= kMaxGraphsPerSlot) drop_graphs(s);
             hipGraph_t g = nullptr;
             hipGraphExec_t ge = nullptr;
             e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);

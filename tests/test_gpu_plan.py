@@ -109,6 +109,28 @@ def test_every_launch_shape(vols, code):
     plan.close()
 
 
+def test_graph_cache_eviction(vols):
+    """Flat-strategy graphs are keyed by the batch's tile counts: 40 batches
+    of distinct sizes overflow the per-table cache (16 graphs) several times
+    over, and every replay still renders what the plain path renders."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Item, Plan
+    vs, _ = vols
+    plan = Plan(vs, max_items=8, use_graph=True, strategy=1)
+    poses = torch.from_numpy(random_poses(8, math.pi / 8, 5.0, 1000.0, seed=77)).to(DEV)
+    for k in range(40):
+        det = P.Detector(16 + 3 * k, 24, 2.0, 2.0)
+        n = 1 + k % 3
+        items = [Item(0, det, poses[j], torch.empty((det.height, 24), device=DEV))
+                 for j in range(n)]
+        plan.execute(items)
+        torch.cuda.synchronize()
+        ref = P.render(vs[0], poses[:n], det)
+        for j, it in enumerate(items):
+            assert torch.equal(it.image, ref[j]), (k, j)
+    plan.close()
+
+
 @pytest.mark.parametrize("strategy", [0, 1, 2])
 def test_plan_is_deterministic(vols, strategy):
     import paper_2208_12737_amd as P
