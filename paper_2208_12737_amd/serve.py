@@ -253,31 +253,38 @@ class GpuBackend:
     def launch(self, tickets: List[Ticket], stream_idx: int):
         """One plan execute for the whole batch: forward items render an
         image, fwd+bwd items also reduce -ZNCC against their target and its
-        pose gradient in the same launch."""
+        pose gradient in the same launch.
+
+        Results are allocated on the caller's current stream (the stream
+        the client will use them on), scratch on the batch's own stream, so
+        that memory a client frees is never handed to a later batch while
+        the client's own work may still read it."""
         torch = self.torch
         from . import _lib
         stream = self.streams[stream_idx]
-        stream.wait_stream(torch.cuda.current_stream())
         n = len(tickets)
         reqs = [t.request for t in tickets]
         host = torch.empty((n, 7), dtype=torch.float32, pin_memory=True)
         host.numpy()[:] = np.stack([np.asarray(r.pose, np.float32) for r in reqs])
         dets = [self._det(r) for r in reqs]
         obj = [k for k, r in enumerate(reqs) if r.kind != FWD]
+        imgs = [torch.empty((r.height, r.width), dtype=torch.float32, device=self.dev)
+                for r in reqs]
+        # loss and gradient of objective item j at lg[j, 0] and lg[j, 1:8]
+        lg = torch.empty((len(obj), 8), dtype=torch.float32, device=self.dev) if obj else None
+        stream.wait_stream(torch.cuda.current_stream())
         out = [None] * n
         arr = (_lib.WorkItem * n)()
         with torch.cuda.stream(stream):
             poses = host.to(self.dev, non_blocking=True)
-            lg = parts = None
+            parts = None
             if obj:
-                # loss and gradient of objective item j at lg[j, 0] and lg[j, 1:8]
-                lg = torch.empty((len(obj), 8), dtype=torch.float32, device=self.dev)
                 parts = torch.empty(sum(dets[k][1] for k in obj), dtype=torch.float64,
                                     device=self.dev)
             pbase = poses.data_ptr()
             j = poff = 0
             for k, r in enumerate(reqs):
-                img = torch.empty((r.height, r.width), dtype=torch.float32, device=self.dev)
+                img = imgs[k]
                 w = arr[k]
                 w.volume = self.index[r.volume]
                 w.det = dets[k][0]
@@ -297,8 +304,8 @@ class GpuBackend:
             _lib.call("drr_plan_execute", self.plan._h, arr, n, stream.cuda_stream)
             ev = torch.cuda.Event()
             ev.record(stream)
-        # the host pose buffer, the pose copy and the scratch stay referenced
-        # until the batch completes
+        # the host pose buffer, the pose copy, the scratch and the requests
+        # (their targets) stay referenced until the batch completes
         return (ev, out, (host, poses, parts, reqs))
 
     def poll(self, h) -> bool:
