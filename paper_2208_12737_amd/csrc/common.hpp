@@ -139,15 +139,15 @@ inline DetArgs det_args(const drr_detector_desc& d)
 
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
-// Dynamic LDS to reserve per workgroup so that at most `wg_per_cu`
-// workgroups are resident on a CU (0 = no limit), for a kernel that already
-// uses `static_bytes` of LDS.  The request never exceeds what one workgroup
-// may allocate: a larger one is rejected when the dispatch starts and
-// aborts the queue.
-inline size_t occupancy_lds(int wg_per_cu, size_t static_bytes)
+struct LdsLimits {
+    size_t per_cu, per_block;
+};
+
+// LDS per CU and per workgroup, queried once (thread-safe initialisation of
+// a function-local static) on the device current at the first launch.
+inline LdsLimits lds_limits()
 {
-    static int lds_per_cu = -1, lds_per_block = -1;
-    if (lds_per_cu < 0) {
+    static const LdsLimits lim = [] {
         int dev = 0, v = 0, b = 0;
         if (hipGetDevice(&dev) != hipSuccess) dev = 0;
         if (hipDeviceGetAttribute(&v, hipDeviceAttributeMaxSharedMemoryPerMultiprocessor, dev) !=
@@ -156,16 +156,27 @@ inline size_t occupancy_lds(int wg_per_cu, size_t static_bytes)
         if (hipDeviceGetAttribute(&b, hipDeviceAttributeMaxSharedMemoryPerBlock, dev) !=
                 hipSuccess || b <= 0)
             b = 64 * 1024;
-        lds_per_cu = v;
-        lds_per_block = b < v ? b : v;
-    }
+        return LdsLimits{(size_t)v, (size_t)(b < v ? b : v)};
+    }();
+    return lim;
+}
+
+// Dynamic LDS to reserve per workgroup so that at most `wg_per_cu`
+// workgroups are resident on a CU (0 = no limit), for a kernel that already
+// uses `static_bytes` of LDS.  The request never exceeds what one workgroup
+// may allocate: a larger one is rejected when the dispatch starts and
+// aborts the queue.
+inline size_t occupancy_lds(int wg_per_cu, size_t static_bytes)
+{
+    const LdsLimits lim = lds_limits();
+    const size_t lds_per_cu = lim.per_cu, lds_per_block = lim.per_block;
     if (wg_per_cu <= 0) return 0;
     // the workgroup's whole allocation (static + dynamic) is its share of
     // the CU, less a margin for allocation granularity
-    const size_t share = (size_t)lds_per_cu / (size_t)wg_per_cu;
+    const size_t share = lds_per_cu / (size_t)wg_per_cu;
     const size_t used = static_bytes + 512;
     size_t dyn = share > used ? share - used : 0;
-    const size_t cap = (size_t)lds_per_block > used ? (size_t)lds_per_block - used : 0;
+    const size_t cap = lds_per_block > used ? lds_per_block - used : 0;
     return dyn < cap ? dyn : cap;
 }
 

@@ -4,6 +4,8 @@
 // enqueues kernels; it never allocates device memory.
 #include <string.h>
 
+#include <atomic>
+
 #include "common.hpp"
 #include "reduce_kernels.hpp"
 
@@ -47,12 +49,14 @@ using DefaultShape = TileShape<kTW, kWX, kWY>;
 // 16 x 16-pixel tiles it was the fastest setting for the image and the fused
 // gradient modes on the 512 x 512 x 133 CT workload (fewer resident rays keep
 // their gathers' lines in the 32 KB L1)
-static int g_wg_per_cu = -1;
+// set by drr_set_launch_occupancy, read by every direct launch (any thread)
+static std::atomic<int> g_wg_per_cu{-1};
 
 static int wg_per_cu_for(const drr_volume_desc& vol)
 {
     (void)vol;
-    return g_wg_per_cu >= 0 ? g_wg_per_cu : 4;
+    const int w = g_wg_per_cu.load(std::memory_order_relaxed);
+    return w >= 0 ? w : 4;
 }
 
 struct FlatGrid {
@@ -110,7 +114,7 @@ int32_t drr_set_launch_occupancy(int32_t wg_per_cu)
 {
     if (wg_per_cu < -1 || wg_per_cu > 64)
         return fail(DRR_EINVAL, "set_launch_occupancy: %d outside [-1, 64]", wg_per_cu);
-    g_wg_per_cu = wg_per_cu;
+    g_wg_per_cu.store(wg_per_cu, std::memory_order_relaxed);
     return DRR_OK;
 }
 
