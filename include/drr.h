@@ -230,11 +230,13 @@ int32_t drr_pose_momentum_step(float* poses, float* velocity, const float* grad_
 /* ---------------------------------------------------------------- plans */
 
 /* A plan batches heterogeneous render work -- any mix of resident volumes,
- * detector sizes and poses, with or without a Jacobian -- into one
- * persistent launch whose workgroups pull ray tiles from a device queue.
- * The launch is captured once into a HIP graph and replayed; the tile shape
- * and occupancy are chosen by an autotuner (timed candidates, cached on disk
- * when a cache path is given). */
+ * detector sizes and poses, rendering images, Jacobians, gather counts or
+ * the fused -ZNCC objective -- into one execute: per output group, a
+ * persistent launch whose workgroups pull ray tiles from device queues, or
+ * one workgroup per tile (DRR_PLAN_* below).  With use_graph the launches
+ * are captured into HIP graphs and replayed; the tile shape and occupancy
+ * are fixed or chosen by an autotuner (timed candidates, cached on disk when
+ * a cache path is given). */
 
 #define DRR_ITEM_JAC 1      /* also write the Jacobian to item.jac */
 #define DRR_ITEM_COUNT 2    /* also write per-pixel gather counts to item.counts */

@@ -1,16 +1,19 @@
 // Batched render plans: heterogeneous work items (volume, detector, pose,
-// outputs) rendered by persistent kernels that pull ray tiles from device
-// queues, optionally replayed from captured HIP graphs, with the launch
-// shape chosen by timing candidates (autotuner).
+// outputs) rendered in one execute, either by persistent kernels that pull
+// ray tiles from device queues or by one workgroup per tile (chosen per
+// output group, or fixed), optionally replayed from captured HIP graphs,
+// with the launch shape chosen by timing candidates (autotuner).
 //
-// Queues.  Each execute call groups its items by output mode (image /
+// Groups.  Each execute call groups its items by output mode (image /
 // image + counts / image + Jacobian / fused -ZNCC objective) and lays the
 // tiles of each group out item after item.  Items of the objective group
 // write per-tile moment sums to their own scratch; a finalize kernel, one
 // workgroup per item, then reduces them in a fixed order into the item's
-// loss and pose gradient.  The tile range of a group is split into 8 contiguous
-// shares, one per XCD; a workgroup first drains the share of the XCD it
-// runs on (hardware dispatch is round-robin over the XCDs), so concurrently
+// loss and pose gradient.
+//
+// Queues.  The tile range of a group is split into 8 contiguous shares, one
+// per XCD; a persistent workgroup first drains the share of the XCD it runs
+// on (hardware dispatch is round-robin over the XCDs), so concurrently
 // running workgroups of one XCD render neighbouring tiles of one pose and
 // share that XCD's L2, and then helps the other shares.  The counters are
 // reset by a small kernel at the start of every execute (no memset nodes in
