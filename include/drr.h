@@ -61,7 +61,9 @@ extern "C" {
 #define DRR_EINVAL (-1)   /* bad argument: NULL pointer, size <= 0, non-finite descriptor */
 #define DRR_ENOMEM (-2)   /* caller workspace too small, or plan allocation failed */
 #define DRR_EHIP (-3)     /* HIP runtime error (launch, copy, graph) */
-#define DRR_ENOTSUP (-4)  /* unsupported size (e.g. volume beyond 2^30 packed voxels) */
+#define DRR_ENOTSUP (-4)  /* unsupported size: a packed volume copy of 4 GiB or more (the
+                             gathers use 32-bit byte offsets), a detector of more than
+                             2^30 pixels, or more than 2^31 - 1 tiles in one launch */
 
 /* Memory layouts of the packed volume.  Both hold the voxels surrounded by a
  * one-voxel border of zeros and give bitwise identical renders; they differ
