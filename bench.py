@@ -833,6 +833,12 @@ def main():
         res["fwdbwd_p50_ms"] = float(np.percentile(times["fwdbwd"], 50))
         res["fwdbwd_p99_ms"] = float(np.percentile(times["fwdbwd"], 99))
         res["gvox_gathers_per_s_fwdbwd"] = gathers_bwd / t_fb / 1e9
+        # algorithmic bytes of the fused kernel: gathers + the target read
+        # (losses and gradients are a few bytes per pose)
+        fb_bytes = 4 * gathers_bwd + 4 * pixels
+        res["fwdbwd_roofline"] = {"bound": "valu", "algorithmic_GBps": fb_bytes / t_fb / 1e9,
+                                  "hbm_frac": fb_bytes / t_fb / 8.0e12,
+                                  "bytes_per_launch": fb_bytes}
         if "value" not in res:
             res["value"] = nb / t_fb
     res["p50_ms"] = float(np.percentile(step_ms, 50))
