@@ -813,6 +813,8 @@ def main():
                            "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
                            "traffic": prof.get("traffic_bytes_per_launch"),
                            "l2_hit_rate": prof.get("l2_hit_rate"),
+                           "l2_GBps": (prof["l2_request_bytes_per_launch"] / t_fwd / 1e9
+                                       if prof.get("l2_request_bytes_per_launch") else None),
                            "profiled_avg_us": prof.get("avg_duration_us"),
                            "gather_floor_ms": (prof["gather_floor_us"] / 1e3
                                                if "gather_floor_us" in prof else None),
