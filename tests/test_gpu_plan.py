@@ -109,6 +109,33 @@ def test_every_launch_shape(vols, code):
     plan.close()
 
 
+def test_full_capacity_table():
+    """The largest item table (8192 items) in one execute, under each
+    strategy, with two detector sizes alternating (so each tile's item is
+    found by the binary search) and with one size (found by division): every
+    item renders what one batched direct call renders."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.plan import Item, Plan
+    ph = make_phantom("small", seed=2)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    n = 8192
+    dets = [P.Detector(6, 5, 6.0, 6.0), P.Detector(9, 7, 5.0, 4.0)]
+    poses = torch.from_numpy(random_poses(n, math.pi / 8, 10.0, 1000.0, seed=31)).to(DEV)
+    for mixed in (True, False):
+        det_of = [dets[k % 2] if mixed else dets[0] for k in range(n)]
+        for strategy in (0, 1, 2):
+            plan = Plan([vol], max_items=n, use_graph=False, strategy=strategy)
+            imgs = [torch.full((d.height, d.width), float("nan"), device=DEV) for d in det_of]
+            plan.execute([Item(0, det_of[k], poses[k], imgs[k]) for k in range(n)])
+            torch.cuda.synchronize()
+            for parity in ((0, 1) if mixed else (0,)):
+                ks = list(range(parity, n, 2 if mixed else 1))
+                ref = P.render(vol, poses[ks], det_of[ks[0]])
+                got = torch.stack([imgs[k] for k in ks])
+                assert torch.equal(got, ref), (mixed, strategy, parity)
+            plan.close()
+
+
 def test_graph_cache_eviction(vols):
     """Flat-strategy graphs are keyed by the batch's tile counts: 40 batches
     of distinct sizes overflow the per-table cache (16 graphs) several times
