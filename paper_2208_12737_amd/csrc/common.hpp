@@ -139,6 +139,20 @@ inline DetArgs det_args(const drr_detector_desc& d)
 
 inline hipStream_t as_stream(void* s) { return (hipStream_t)s; }
 
+// Compute units of the device current at the first launch (queried once).
+inline int num_cus()
+{
+    static const int n = [] {
+        int dev = 0, v = 0;
+        if (hipGetDevice(&dev) != hipSuccess) dev = 0;
+        if (hipDeviceGetAttribute(&v, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess ||
+            v <= 0)
+            v = 256;
+        return v;
+    }();
+    return n;
+}
+
 struct LdsLimits {
     size_t per_cu, per_block;
 };

@@ -150,7 +150,8 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
         o.counts = it.counts;
         o.aux = MODE == kNcc ? it.target : nullptr;
         o.partial = MODE == kNcc ? it.partials + (int64_t)local * kNccSums : nullptr;
-        render_tile<TW, WX, WY, MODE>(it.vol, it.det, it.pose, tx, ty, o, lds);
+        render_tile<TW, WX, WY, MODE, full_depth<MODE>()>(it.vol, it.det, it.pose, tx, ty, o,
+                                                           lds);
     }
     (void)sizeof(S);
 }
@@ -175,7 +176,9 @@ __global__ __launch_bounds__(64 * WX * WY) void render_plan_flat(const char* __r
     o.counts = it.counts;
     o.aux = MODE == kNcc ? it.target : nullptr;
     o.partial = MODE == kNcc ? it.partials + (int64_t)local * kNccSums : nullptr;
-    render_tile<TW, WX, WY, MODE>(it.vol, it.det, it.pose, tx, ty, o, lds);
+    // the flat grid serves small groups under the default strategy: the deep
+    // pipeline keeps a lone wave's gathers in flight
+    render_tile<TW, WX, WY, MODE, kDeepDepth>(it.vol, it.det, it.pose, tx, ty, o, lds);
 }
 
 // Loss and pose gradient of every objective item: workgroup i reduces the

@@ -30,11 +30,11 @@ constexpr uint32_t kBufferDword3 = 0x00020000u;  // gfx9 raw buffer, 32-bit data
 // always includes every segment.
 constexpr double kSliver = 0x1p-36;
 
-// Crossings the merge runs ahead of the accumulation (1 or 2).
-#ifndef DRR_PREFETCH_DEPTH
-#define DRR_PREFETCH_DEPTH 2
-#endif
-constexpr int kDepth = DRR_PREFETCH_DEPTH;
+// Deepest gather pipeline (crossings the merge runs ahead of the
+// accumulation; the launches choose 2 or 4).  The depth changes only when
+// loads are issued, never the order of the arithmetic: results are bitwise
+// the same at any depth.
+constexpr int kDeepDepth = 4;
 
 // A packed volume: one or three copies of the zero-bordered grid, each in
 // its own memory order.  pitch[q][c] is the byte distance between
@@ -157,10 +157,11 @@ __device__ inline double min_nn(double a, double b)
 // |d| / |d_DERIVED| stays small for every ray of the wave.  (A template
 // argument: with a run-time axis the compiler selects between the per-lane
 // crossing masks with several VALU instructions per step.)
-template <bool JAC, bool COUNT, int DERIVED>
+template <bool JAC, bool COUNT, int DERIVED, int DEPTH>
 __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
                                const int32_t pitch[3], const double s[3], const double d[3])
 {
+    static_assert(DEPTH == 1 || DEPTH == 2 || DEPTH == 4, "prefetch depth 1, 2 or 4");
     constexpr int derived = DERIVED;
     RayAcc r;
     r.sum = 0.0;
@@ -248,8 +249,8 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
 
     // The traversal is split into a merge (pick the next crossing, advance
     // that axis, issue the gather of the voxel beyond it) and an accumulation
-    // (add a closed segment's length x value).  The merge runs kDepth
-    // crossings ahead of the accumulation, so every gather has kDepth merge
+    // (add a closed segment's length x value).  The merge runs DEPTH
+    // crossings ahead of the accumulation, so every gather has DEPTH merge
     // steps of independent work between its issue and its use.  Register
     // names rotate through an unrolled loop instead of being copied: a copy
     // of a loaded value would force an early wait on the load.
@@ -313,7 +314,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // steps of an iteration run for a live lane (steps after the exit close
     // empty segments), which keeps each load ahead of its use.
     bool active = true;
-    if (kDepth == 1) {
+    if (DEPTH == 1) {
         float v0 = ld(rsrc, off), v1 = 0.0f;
         double a0 = amin, a1 = amin;
         float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f;
@@ -328,7 +329,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
             }
             if (__builtin_amdgcn_ballot_w64(active) == 0) break;
         }
-    } else {
+    } else if (DEPTH == 2) {
         // segment m = [a_m, a_{m+1}] with value v_m is closed while the merge
         // produces crossing m + 2; names rotate with period three
         float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f;
@@ -344,6 +345,33 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
                 DRR_ACCUM(v1, a1, a2, p1, q1);
                 DRR_MERGE(v1, a1, p1, q1);
                 DRR_ACCUM(v2, a2, a0, p2, q2);
+                active = a0 < amax;
+            }
+            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+        }
+    } else {
+        // depth 4: segment m is closed while the merge produces crossing
+        // m + 4; names rotate with period five
+        float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
+        double a0 = amin, a1 = amin, a2 = amin, a3 = amin, a4 = amin;
+        float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f, p2 = 0.0f, q2 = 0.0f,
+              p3 = 0.0f, q3 = 0.0f, p4 = 0.0f, q4 = 0.0f;
+        DRR_MERGE(v1, a1, p1, q1);
+        DRR_MERGE(v2, a2, p2, q2);
+        DRR_MERGE(v3, a3, p3, q3);
+        const int cap = (V.n[0] + V.n[1] + V.n[2] + 14) / 5;
+        for (int it = 0; it < cap; ++it) {
+            if (active) {
+                DRR_MERGE(v4, a4, p4, q4);
+                DRR_ACCUM(v0, a0, a1, p0, q0);
+                DRR_MERGE(v0, a0, p0, q0);
+                DRR_ACCUM(v1, a1, a2, p1, q1);
+                DRR_MERGE(v1, a1, p1, q1);
+                DRR_ACCUM(v2, a2, a3, p2, q2);
+                DRR_MERGE(v2, a2, p2, q2);
+                DRR_ACCUM(v3, a3, a4, p3, q3);
+                DRR_MERGE(v3, a3, p3, q3);
+                DRR_ACCUM(v4, a4, a0, p4, q4);
                 active = a0 < amax;
             }
             if (__builtin_amdgcn_ballot_w64(active) == 0) break;
