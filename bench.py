@@ -139,10 +139,20 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
     oracle.render(grid, p64[:1], det_px, det_px, pitch, pitch, rows=(r0, r0 + rows), nthreads=1)
     dt1 = time.perf_counter() - t0
     # the differentiable-render workload: 200 x 200 detector, image + pose
-    # Jacobian, two poses on all threads
+    # Jacobian, eight poses on all threads
+    nj = min(8, len(p64))
     t0 = time.perf_counter()
-    oracle.render_jacobian(grid, p64[:2], 200, 200, pitch, pitch, nthreads=nthreads)
+    oracle.render_jacobian(grid, p64[:nj], 200, 200, pitch, pitch, nthreads=nthreads)
     dt_j = time.perf_counter() - t0
+    # the small parity workload: 64^3 phantom at 1 mm, 64 x 64 detector at
+    # 2 mm, SDD 1000 mm, one thread
+    from synth import make_phantom, random_poses
+    sm = make_phantom("small", seed=0)
+    sgrid = oracle.Grid(sm.volume, sm.spacing, sm.origin)
+    sp = random_poses(4, math.pi / 8, 10.0, 1000.0, seed=0).astype(np.float64)
+    t0 = time.perf_counter()
+    oracle.render(sgrid, sp, 64, 64, 2.0, 2.0, nthreads=1)
+    dt_s = time.perf_counter() - t0
     model = ""
     try:
         with open("/proc/cpuinfo") as fh:
@@ -159,9 +169,12 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
             "single_thread": {"value": rows / det_px / dt1, "unit": "DRRs/s",
                               "sample": f"rows {r0}..{r0 + rows - 1} of one DRR "
                                         f"({rows * det_px} rays), {dt1:.2f} s on 1 thread"},
-            "fwd_jacobian_200x200": {"value": 2 / dt_j, "unit": "DRRs/s",
-                                     "sample": f"2 DRRs of 200x200 with d image / d pose, "
+            "fwd_jacobian_200x200": {"value": nj / dt_j, "unit": "DRRs/s",
+                                     "sample": f"{nj} DRRs of 200x200 with d image / d pose, "
                                                f"{dt_j:.2f} s on {nthreads} threads"},
+            "small_64cube_det64": {"value": 4 / dt_s, "unit": "DRRs/s",
+                                   "sample": f"4 DRRs of 64x64 on the 64^3 phantom, "
+                                             f"{dt_s:.3f} s on 1 thread"},
             "cpu_model": model, "nproc": os.cpu_count()}
 
 
