@@ -178,6 +178,23 @@ def test_deterministic_and_batch_independent(small):
         assert torch.equal(alone[0], a[k])
 
 
+def test_pipeline_depth_does_not_change_results(small):
+    """Launches of up to 16 workgroups per CU run the depth-4 gather
+    pipeline, larger image launches depth 2: a pose renders bitwise the same
+    in a batch of 8 (depth 4) and in a batch of 300 (depth 2, 300 x 256
+    workgroups), and so do its gather counts."""
+    P = _lib_objs()
+    ph, vol, grid = small
+    det = P.Detector(256, 256, 0.5, 0.5)          # 256 workgroups per pose
+    poses = _gpu(random_poses(300, math.pi / 8, 10.0, 1000.0, seed=23))
+    big = P.render(vol, poses, det)
+    few = P.render(vol, poses[:8].clone(), det)
+    assert torch.equal(few, big[:8])
+    big_i, big_c = P.render_count(vol, poses, det)
+    few_i, few_c = P.render_count(vol, poses[:8].clone(), det)
+    assert torch.equal(few_c, big_c[:8]) and torch.equal(few_i, big_i[:8])
+
+
 # ------------------------------------------------------------------ clinical size
 
 def test_ct512_batched_launch_sampled(ct512):
