@@ -26,9 +26,10 @@ def assert_image_close(gpu, ref, rtol=IMAGE_RTOL, what="image"):
 
 
 def column_errors(gpu, ref):
-    """Per-parameter error of Jacobians [..., 7] relative to each column's
-    largest magnitude."""
-    gpu = np.asarray(gpu, dtype=np.float64).reshape(-1, 7)
-    ref = np.asarray(ref, dtype=np.float64).reshape(-1, 7)
+    """Per-parameter error of Jacobians [..., k] (k = 7 pose parameters, or 4
+    detector parameters) relative to each column's largest magnitude."""
+    k = np.shape(ref)[-1]
+    gpu = np.asarray(gpu, dtype=np.float64).reshape(-1, k)
+    ref = np.asarray(ref, dtype=np.float64).reshape(-1, k)
     scale = np.abs(ref).max(axis=0) + 1e-300
     return np.abs(gpu - ref).max(axis=0) / scale

@@ -70,6 +70,37 @@ def test_sampled_poses_match_oracle_image_and_jacobian(batch, b):
     assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (grad[b], ref)
 
 
+@pytest.mark.parametrize("b", [12, 40])
+def test_fused_l2_at_clinical_size(batch, b):
+    """The L2 objective (mean squared difference) fused over the same 64-pose
+    launch: sampled poses' loss and pose gradient against the oracle's image,
+    Jacobian and L2 gradient."""
+    P, vol, grid, det, gt, poses, target, loss, grad, img, jac = batch
+    pt = torch.from_numpy(poses).to(DEV)
+    l2, g2 = P.render_l2(vol, pt, det, target)
+    rimg, rjac = oracle.render_jacobian(grid, poses[b:b + 1].astype(np.float64), H, W, PITCH,
+                                        PITCH, nthreads=8)
+    T = target.cpu().numpy().astype(np.float64)
+    v, gi = oracle.l2_grad(rimg[0], T)
+    assert l2[b].item() == pytest.approx(v, rel=1e-5)
+    ref = np.einsum("hw,hwj->j", gi, rjac[0])
+    scale = np.abs(gi).sum() * np.abs(rjac[0]).max(axis=(0, 1))
+    assert np.all(np.abs(g2[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (g2[b], ref)
+
+
+def test_detector_jacobian_at_clinical_size(batch):
+    """d image / d (delta_x, delta_y, offset_u, offset_v) of one pose of the
+    batch, every pixel, against the oracle's frozen-index derivative."""
+    P, vol, grid, det, gt, poses, target, loss, grad, img, jac = batch
+    b = 21
+    dimg, djac = P.render_detector_jacobian(vol, torch.from_numpy(poses[b:b + 1]).to(DEV), det)
+    rimg, rjac = oracle.render_detector_jacobian(grid, poses[b:b + 1].astype(np.float64), H, W,
+                                                 PITCH, PITCH, nthreads=8)
+    assert_image_close(dimg.cpu().numpy(), rimg)
+    errs = column_errors(djac[0].cpu().numpy().astype(np.float64), rjac[0])
+    assert max(errs) <= JAC_RTOL, errs
+
+
 def test_batch_gradient_equals_unfused_path(batch):
     """Fused objective = render -> NCC loss -> stored-Jacobian backward, on
     all 64 poses of the launch."""
