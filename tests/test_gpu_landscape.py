@@ -73,3 +73,26 @@ def test_l2_landscape_minimum_at_ground_truth(setup):
     np.testing.assert_allclose(loss, full.cpu().numpy(), rtol=1e-6, atol=0)
     frac, _ = radial_monotonicity(vol, det, gt, n_dirs=16, n_steps=6, radius=0.1, loss="l2")
     assert frac >= 0.75
+
+
+def test_landscape_in_the_benchmark_configuration():
+    """The sweep as benchmarked: the 512 x 512 x 133 CT, a 256 x 256 detector
+    at 1.4 mm, 8192 offsets of the paper's box in one launch; sampled poses'
+    -ZNCC against the oracle's DRR and the same target."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.landscape import random_offsets, sweep
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    det = P.Detector(256, 256, 1.4, 1.4)
+    gt = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=21)[0]
+    off = random_offsets(8192, seed=22)
+    target = P.render(vol, torch.from_numpy(gt[None]).to(DEV), det)[0]
+    loss = sweep(vol, det, gt, off, chunk=8192, target=target)
+    assert np.all(np.isfinite(loss)) and np.all(np.abs(loss) <= 1.0 + 1e-6)
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    T = target.cpu().numpy().astype(np.float64)
+    rng = np.random.default_rng(6)
+    for k in rng.choice(8192, 4, replace=False):
+        pose = (gt + off[k]).astype(np.float32).astype(np.float64)
+        img, _, _ = oracle.render(grid, pose, 256, 256, 1.4, 1.4, nthreads=8)
+        assert loss[k] == pytest.approx(-oracle.zncc(img[0], T), abs=2e-6), k
