@@ -100,3 +100,49 @@ def test_bad_requests_fail_at_submission(volumes):
     with pytest.raises(ValueError):       # invalid detector
         srv.submit(Request("a", 0, 8, 1.0, 1.0, pose, FWD))
     assert srv.pending() == 0
+
+
+def test_serving_mix_in_the_benchmark_configuration():
+    """The benchmark's four resident volumes (128^3 at 2 mm, 256^3 at 1 mm,
+    512 x 512 x 133 and 512 x 512 x 300) and four detector sizes (pitch
+    358.4 mm / N): every volume and detector pair as a forward request, half
+    of them also as forward + backward requests, served under a small budget;
+    forward results equal the plain single-DRR path and fwd+bwd results equal
+    the fused call, bit for bit."""
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd.serve import FWD, FWDBWD, GpuBackend, Request, Server, plain_forward
+    names = ["ct128", "ct256", "ct512", "ct512x300"]
+    vols = {}
+    for nm in names:
+        ph = make_phantom(nm, seed=0)
+        vols[nm] = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    reqs = []
+    for i, nm in enumerate(names):
+        for j, N in enumerate((128, 200, 256, 512)):
+            px = 358.4 / N
+            pose = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=100 + 4 * i + j)[0]
+            reqs.append(Request(nm, N, N, px, px, pose, FWD))
+            if (i + j) % 2 == 0:
+                gt = pose.copy()
+                gt[:3] += 0.03
+                tg = P.render(vols[nm], torch.from_numpy(gt).to(DEV)[None],
+                              P.Detector(N, N, px, px))[0]
+                reqs.append(Request(nm, N, N, px, px, pose, FWDBWD, tg))
+    srv = Server(GpuBackend(vols, n_streams=3), hbm_budget_bytes=8 << 20, n_streams=3,
+                 max_batch=6)
+    tickets = [srv.submit(r) for r in reqs]
+    srv.run_until_idle()
+    torch.cuda.synchronize()
+    assert srv.batches >= 4
+    for r, t in zip(reqs, tickets):
+        got = t.wait(0)
+        det = P.Detector(r.height, r.width, r.delta_x, r.delta_y)
+        if r.kind == FWD:
+            assert torch.equal(got, plain_forward(vols, r))
+        else:
+            img, loss, grad = got
+            pose = torch.from_numpy(np.asarray(r.pose, np.float32)).to(DEV)[None]
+            l_ref, g_ref, i_ref = P.render_ncc_grad(vols[r.volume], pose, det, r.target,
+                                                    return_image=True)
+            assert torch.equal(img, i_ref[0])
+            assert torch.equal(loss.reshape(1), l_ref) and torch.equal(grad, g_ref[0])
