@@ -152,3 +152,41 @@ def test_packed_copy_size_limit():
     assert lib.drr_volume_packed_bytes(ctypes.byref(big)) == 0
     assert lib.drr_volume_pack(None, None, ctypes.byref(big), None) == _lib.DRR_ENOTSUP
     assert b"4 GiB" in lib.drr_last_error()
+
+
+def test_header_is_plain_c(tmp_path):
+    """include/drr.h compiles as strict C99, and a C program links against
+    libdrr.so and calls its host-only entry points (no GPU needed)."""
+    import shutil
+    import subprocess
+    gcc = shutil.which("gcc")
+    if gcc is None:
+        pytest.skip("no C compiler")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    src = tmp_path / "use_drr.c"
+    src.write_text(r"""
+#include <stdio.h>
+#include "drr.h"
+int main(void)
+{
+    drr_detector_desc det = {64, 64, 1.0, 1.0, 0.0, 0.0};
+    drr_volume_desc vol = {4, 5, 6, {1.0, 1.0, 1.0}, {0.0, 0.0, 0.0}, DRR_LAYOUT_INPUT};
+    if (drr_version() < 10000) return 1;
+    if (drr_plan_item_workspace_bytes(&det) != (size_t)64 * 26 * 8) return 2;
+    if (drr_volume_packed_bytes(&vol) != (size_t)6 * 7 * 8 * 4) return 3;
+    det.height = 0;
+    if (drr_render(NULL, &vol, &det, NULL, 1, NULL, NULL, NULL) != DRR_EINVAL) return 4;
+    if (drr_last_error()[0] == '\0') return 5;
+    puts(drr_status_string(DRR_OK));
+    return 0;
+}
+""")
+    libdir = os.path.join(root, "paper_2208_12737_amd")
+    exe = tmp_path / "use_drr"
+    res = subprocess.run([gcc, "-std=c99", "-Wall", "-Wextra", "-Werror", "-pedantic",
+                          "-I", os.path.join(root, "include"), str(src), "-L", libdir, "-ldrr",
+                          f"-Wl,-rpath,{libdir}", "-o", str(exe)], capture_output=True, text=True)
+    assert res.returncode == 0, res.stderr
+    run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
+    assert run.returncode == 0, (run.returncode, run.stderr)
+    assert run.stdout.strip() == "ok"
