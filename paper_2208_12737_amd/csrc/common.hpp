@@ -10,6 +10,7 @@
 #include <stdio.h>
 
 #include "../../include/drr.h"
+#include "launch_budget.hpp"
 #include "siddon.hpp"
 
 namespace drr {
@@ -153,10 +154,6 @@ inline int num_cus()
     return n;
 }
 
-struct LdsLimits {
-    size_t per_cu, per_block;
-};
-
 // LDS per CU and per workgroup, queried once (thread-safe initialisation of
 // a function-local static) on the device current at the first launch.
 inline LdsLimits lds_limits()
@@ -175,23 +172,11 @@ inline LdsLimits lds_limits()
     return lim;
 }
 
-// Dynamic LDS to reserve per workgroup so that at most `wg_per_cu`
-// workgroups are resident on a CU (0 = no limit), for a kernel that already
-// uses `static_bytes` of LDS.  The request never exceeds what one workgroup
-// may allocate: a larger one is rejected when the dispatch starts and
-// aborts the queue.
+// Dynamic LDS that caps residency at `wg_per_cu` workgroups per CU on this
+// device (see occupancy_lds_bytes).
 inline size_t occupancy_lds(int wg_per_cu, size_t static_bytes)
 {
-    const LdsLimits lim = lds_limits();
-    const size_t lds_per_cu = lim.per_cu, lds_per_block = lim.per_block;
-    if (wg_per_cu <= 0) return 0;
-    // the workgroup's whole allocation (static + dynamic) is its share of
-    // the CU, less a margin for allocation granularity
-    const size_t share = lds_per_cu / (size_t)wg_per_cu;
-    const size_t used = static_bytes + 512;
-    size_t dyn = share > used ? share - used : 0;
-    const size_t cap = lds_per_block > used ? lds_per_block - used : 0;
-    return dyn < cap ? dyn : cap;
+    return occupancy_lds_bytes(lds_limits(), wg_per_cu, static_bytes);
 }
 
 }  // namespace drr

@@ -29,20 +29,11 @@ int32_t check_launch(const char* what)
     return DRR_OK;
 }
 
-// Launch shape of the direct (non-plan) entry points: 4 x 16-pixel wave
-// tiles (4 columns, 16 rows), 4 waves side by side (16 x 16 pixels, 256
-// threads).  Of nine shapes timed on the 256-pose CT batch this one was the
-// fastest for the image mode and level with the best for the fused gradient.
-// Fewer resident workgroups per CU than the register file allows keep the
-// gather working set inside the L1/L2 caches; the limit is imposed by
-// reserving LDS per workgroup (default 4 workgroups = 4 waves per SIMD).
-#ifndef DRR_DIRECT_SHAPE
-#define DRR_DIRECT_SHAPE 4, 4, 1
-#endif
-// Tile shape of the direct launches: pixels per wave row, waves per
-// workgroup along w and along h.
-constexpr int kShape[3] = {DRR_DIRECT_SHAPE};
-constexpr int kTW = kShape[0], kWX = kShape[1], kWY = kShape[2];
+// Launch shape of the direct (non-plan) entry points (kDirectShape).  Fewer
+// resident workgroups per CU than the register file allows keep the gather
+// working set inside the L1/L2 caches; the limit is imposed by reserving LDS
+// per workgroup (default 4 workgroups = 4 waves per SIMD).
+constexpr int kTW = kDirectShape.tw, kWX = kDirectShape.wx, kWY = kDirectShape.wy;
 using DefaultShape = TileShape<kTW, kWX, kWY>;
 
 // -1: the default, 4 resident workgroups per CU: with 4 x 16-pixel waves in
@@ -76,8 +67,7 @@ static FlatGrid flat_grid(const drr_detector_desc& d)
 template <int MODE>
 static constexpr size_t flat_static_lds()
 {
-    return sizeof(double) * (size_t)(ModeTraits<MODE>::nsum > 0 ? ModeTraits<MODE>::nsum : 1) *
-           (size_t)(kWX * kWY);
+    return tile_sum_lds_bytes(ModeTraits<MODE>::nsum, kWX * kWY);
 }
 
 template <int MODE>

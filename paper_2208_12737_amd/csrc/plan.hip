@@ -127,6 +127,9 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
     using S = TileShape<TW, WX, WY>;
     __shared__ int s_tile;
     __shared__ double lds[MODE == kNcc ? kNccSums * WX * WY : 1];
+    static_assert(sizeof(lds) + sizeof(s_tile) <=
+                      16 + tile_sum_lds_bytes(MODE == kNcc ? kNccSums : 0, WX * WY),
+                  "static LDS budget");
     const PlanHeader* hdr = (const PlanHeader*)block;
     const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
     const int first = hdr->first[group], total = hdr->tiles[group];
@@ -164,6 +167,8 @@ __global__ __launch_bounds__(64 * WX * WY) void render_plan_flat(const char* __r
                                                                  int group)
 {
     __shared__ double lds[MODE == kNcc ? kNccSums * WX * WY : 1];
+    static_assert(sizeof(lds) <= 16 + tile_sum_lds_bytes(MODE == kNcc ? kNccSums : 0, WX * WY),
+                  "static LDS budget");
     const PlanHeader* hdr = (const PlanHeader*)block;
     const PlanItem* items = (const PlanItem*)(block + sizeof(PlanHeader));
     const int t = (int)xcd_logical(blockIdx.x, gridDim.x);
@@ -195,23 +200,6 @@ __global__ __launch_bounds__(kReduceThreads) void k_plan_ncc_finalize(
 }
 
 // ------------------------------------------------------------------ shapes
-
-// Candidate launch shapes: wave tile width (pixels) and waves per workgroup.
-struct ShapeInfo {
-    int tw, wx, wy;
-};
-static const ShapeInfo kShapes[] = {
-    {8, 2, 2},    // 0: 16 x 16 px, 8 x 8 wave tiles
-    {8, 1, 1},    // 1:  8 x  8 px
-    {8, 1, 4},    // 2:  8 x 32 px
-    {16, 1, 4},   // 3: 16 x 16 px, 16 x 4 wave tiles
-    {4, 4, 1},    // 4: 16 x 16 px,  4 x 16 wave tiles
-    {8, 4, 1},    // 5: 32 x  8 px
-    {4, 1, 4},    // 6:  4 x 64 px,  4 x 16 wave tiles
-    {2, 2, 2},    // 7:  4 x 64 px,  2 x 32 wave tiles
-    {1, 4, 1},    // 8:  4 x 64 px,  1 x 64 wave tiles
-};
-constexpr int kNumShapes = sizeof(kShapes) / sizeof(kShapes[0]);
 
 typedef void (*PersistentFn)(const char*, int32_t*, int);
 
@@ -285,7 +273,7 @@ static int group_of_flags(int32_t flags)
 // and the block-sum buffer of the objective group.
 static size_t plan_static_lds(int g, const ShapeInfo& sh)
 {
-    return 16 + (group_mode(g) == kNcc ? sizeof(double) * kNccSums * sh.wx * sh.wy : 0);
+    return 16 + tile_sum_lds_bytes(group_mode(g) == kNcc ? kNccSums : 0, sh.wx * sh.wy);
 }
 
 // Tiles of a detector for launch shape `code`.

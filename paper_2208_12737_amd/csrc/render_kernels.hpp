@@ -21,6 +21,7 @@
 //   kL2Loss   image (optional) + per-tile sum of (I-T)^2
 #pragma once
 
+#include "launch_budget.hpp"
 #include "siddon.hpp"
 
 namespace drr {
@@ -29,6 +30,7 @@ enum Mode { kImage = 0, kCount = 1, kJac = 2, kRetrace = 3, kNcc = 4, kNccLoss =
             kJacDet = 6, kL2 = 7, kL2Loss = 8 };
 
 constexpr int kNccSums = 26;
+static_assert(kNccSums <= kMaxTileSums, "tile sums exceed the LDS budget");
 
 template <int MODE>
 struct ModeTraits {
@@ -241,6 +243,7 @@ __global__ __launch_bounds__(64 * WX * WY) void render_flat(
 {
     using T = ModeTraits<MODE>;
     __shared__ double lds[(T::nsum > 0 ? T::nsum : 1) * WX * WY];
+    static_assert(sizeof(lds) == tile_sum_lds_bytes(T::nsum, WX * WY), "static LDS budget");
     const uint32_t logical = xcd_logical(blockIdx.x, gridDim.x);
     const int b = (int)(logical / (uint32_t)wg_per_pose);
     const int t = (int)(logical % (uint32_t)wg_per_pose);

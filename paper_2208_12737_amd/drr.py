@@ -36,6 +36,35 @@ def _poses(poses: torch.Tensor) -> torch.Tensor:
     return p
 
 
+def target_stride(numel: int, n: int, hw: int) -> int:
+    """Element stride between the per-pose targets of a batch of n images of
+    hw pixels: 0 when one image is shared by every pose, hw when there is
+    one per pose.  Any other size would make the kernels read past the
+    tensor, so it is rejected."""
+    if numel == hw:
+        return 0
+    if numel == n * hw:
+        return hw
+    raise ValueError(f"target must hold one image ({hw} elements) or one per pose "
+                     f"({n} x {hw}); got {numel} elements")
+
+
+def _expect_numel(t: torch.Tensor, name: str, numel: int) -> None:
+    if t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()} "
+                         f"(shape {tuple(t.shape)})")
+
+
+def _same_device(device, *named) -> None:
+    for name, t in named:
+        if t is not None and t.device != device:
+            raise ValueError(f"{name} is on {t.device}, expected {device}")
+
+
+def _check_volume(volume: "Volume", p: torch.Tensor) -> None:
+    _same_device(p.device, ("volume", volume.packed))
+
+
 @dataclass(frozen=True)
 class Detector:
     """Detector of height x width pixels; delta_x / delta_y are the column /
@@ -104,6 +133,7 @@ class Volume:
 def render(volume: Volume, poses: torch.Tensor, det: Detector, jacobian: bool = False):
     """DRRs [n, H, W] (and, if asked, Jacobians [n, H, W, 7])."""
     p = _poses(poses)
+    _check_volume(volume, p)
     n = p.shape[0]
     img = torch.empty((n, det.height, det.width), dtype=torch.float32, device=p.device)
     jac = torch.empty((n, det.height, det.width, 7), dtype=torch.float32,
@@ -118,6 +148,7 @@ def render_detector_jacobian(volume: Volume, poses: torch.Tensor, det: Detector)
     """DRRs [n, H, W] and d image / d (delta_x, delta_y, offset_u, offset_v)
     [n, H, W, 4]."""
     p = _poses(poses)
+    _check_volume(volume, p)
     n = p.shape[0]
     img = torch.empty((n, det.height, det.width), dtype=torch.float32, device=p.device)
     jac = torch.empty((n, det.height, det.width, 4), dtype=torch.float32, device=p.device)
@@ -130,6 +161,7 @@ def render_detector_jacobian(volume: Volume, poses: torch.Tensor, det: Detector)
 def render_count(volume: Volume, poses: torch.Tensor, det: Detector):
     """DRRs and per-pixel counts of voxel gathers (positive-length segments)."""
     p = _poses(poses)
+    _check_volume(volume, p)
     n = p.shape[0]
     img = torch.empty((n, det.height, det.width), dtype=torch.float32, device=p.device)
     cnt = torch.empty((n, det.height, det.width), dtype=torch.int32, device=p.device)
@@ -143,11 +175,26 @@ def _workspace(nbytes: int, device) -> torch.Tensor:
     return torch.empty(max(int(nbytes), 8), dtype=torch.uint8, device=device)
 
 
+def _reuse_workspace(ws: torch.Tensor | None, need: int, device):
+    """(pointer owner, size in bytes) of the caller's workspace when it is a
+    contiguous tensor on `device` of at least `need` bytes, else of a fresh
+    one."""
+    if (ws is not None and ws.is_cuda and ws.device == device and ws.is_contiguous()
+            and ws.numel() * ws.element_size() >= need):
+        return ws, ws.numel() * ws.element_size()
+    fresh = _workspace(need, device)
+    return fresh, fresh.numel()
+
+
 def render_backward(det: Detector, jac: torch.Tensor, grad_image: torch.Tensor) -> torch.Tensor:
     """grad_pose[n, 7] = sum over pixels of grad_image * jac."""
     jac = _dev_f32(jac, "jac")
     g = _dev_f32(grad_image, "grad_image")
+    if jac.ndim != 4 or tuple(jac.shape[1:]) != (det.height, det.width, 7):
+        raise ValueError(f"jac must be [n, {det.height}, {det.width}, 7], got {tuple(jac.shape)}")
     n = jac.shape[0]
+    _expect_numel(g, "grad_image", n * det.pixels)
+    _same_device(jac.device, ("grad_image", g))
     out = torch.empty((n, 7), dtype=torch.float32, device=jac.device)
     ws_n = _lib.load().drr_backward_workspace_bytes(ctypes.byref(det.desc), n)
     ws = _workspace(ws_n, jac.device)
@@ -161,8 +208,11 @@ def render_backward_retrace(volume: Volume, poses: torch.Tensor, det: Detector,
     """Same gradient as render_backward, tracing the rays again instead of
     reading a stored Jacobian."""
     p = _poses(poses)
+    _check_volume(volume, p)
     g = _dev_f32(grad_image, "grad_image")
     n = p.shape[0]
+    _expect_numel(g, "grad_image", n * det.pixels)
+    _same_device(p.device, ("grad_image", g))
     out = torch.empty((n, 7), dtype=torch.float32, device=p.device)
     ws_n = _lib.load().drr_backward_workspace_bytes(ctypes.byref(det.desc), n)
     ws = _workspace(ws_n, p.device)
@@ -207,14 +257,12 @@ class _NCCFn(torch.autograd.Function):
     def forward(ctx, image, target):
         img = _dev_f32(image, "image")
         tgt = _dev_f32(target, "target")
+        if img.ndim < 2:
+            raise ValueError(f"image must be [n, ...], got {tuple(img.shape)}")
         n = img.shape[0]
         hw = img[0].numel()
-        if tgt.numel() == hw:
-            tstride = 0
-        elif tgt.numel() == n * hw:
-            tstride = hw
-        else:
-            raise ValueError("target must hold one image or one image per pose")
+        tstride = target_stride(tgt.numel(), n, hw)
+        _same_device(img.device, ("target", tgt))
         stats = torch.empty((n, 5), dtype=torch.float64, device=img.device)
         loss = torch.empty((n,), dtype=torch.float32, device=img.device)
         ws = _workspace(_lib.load().drr_ncc_workspace_bytes(n, hw), img.device)
@@ -229,6 +277,7 @@ class _NCCFn(torch.autograd.Function):
         img, tgt, stats = ctx.saved_tensors
         gl = _dev_f32(grad_loss, "grad_loss")
         n = img.shape[0]
+        _expect_numel(gl, "grad_loss", n)
         out = torch.empty_like(img)
         _lib.call("drr_ncc_backward", img.data_ptr(), tgt.data_ptr(), ctx.tstride,
                   stats.data_ptr(), gl.data_ptr(), n, ctx.hw, out.data_ptr(), _stream())
@@ -244,21 +293,22 @@ def render_ncc_grad(volume: Volume, poses: torch.Tensor, det: Detector, target: 
                     return_image: bool = False, workspace: torch.Tensor | None = None):
     """Fused registration objective: (loss [n], grad_pose [n, 7][, image])."""
     p = _poses(poses)
+    _check_volume(volume, p)
     tgt = _dev_f32(target, "target")
     n = p.shape[0]
     hw = det.pixels
-    tstride = 0 if tgt.numel() == hw else hw
+    tstride = target_stride(tgt.numel(), n, hw)
+    _same_device(p.device, ("target", tgt))
     loss = torch.empty((n,), dtype=torch.float32, device=p.device)
     grad = torch.empty((n, 7), dtype=torch.float32, device=p.device)
     img = torch.empty((n, det.height, det.width), dtype=torch.float32,
                       device=p.device) if return_image else None
     need = _lib.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), n)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(
-        need, p.device)
+    ws, ws_bytes = _reuse_workspace(workspace, need, p.device)
     _lib.call("drr_render_ncc_grad", volume.packed.data_ptr(), ctypes.byref(volume.desc),
               ctypes.byref(det.desc), p.data_ptr(), n, tgt.data_ptr(), tstride,
               img.data_ptr() if img is not None else None, loss.data_ptr(), grad.data_ptr(),
-              ws.data_ptr(), ws.numel(), _stream())
+              ws.data_ptr(), ws_bytes, _stream())
     return (loss, grad, img) if return_image else (loss, grad)
 
 
@@ -267,17 +317,18 @@ def render_ncc_loss(volume: Volume, poses: torch.Tensor, det: Detector, target: 
     """-ZNCC of each pose's DRR against `target` (one shared image or one per
     pose), without storing images or gradients: [n]."""
     p = _poses(poses)
+    _check_volume(volume, p)
     tgt = _dev_f32(target, "target")
     n = p.shape[0]
     hw = det.pixels
-    tstride = 0 if tgt.numel() == hw else hw
+    tstride = target_stride(tgt.numel(), n, hw)
+    _same_device(p.device, ("target", tgt))
     loss = torch.empty((n,), dtype=torch.float32, device=p.device)
     need = _lib.load().drr_ncc_loss_workspace_bytes(ctypes.byref(det.desc), n)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(
-        need, p.device)
+    ws, ws_bytes = _reuse_workspace(workspace, need, p.device)
     _lib.call("drr_render_ncc_loss", volume.packed.data_ptr(), ctypes.byref(volume.desc),
               ctypes.byref(det.desc), p.data_ptr(), n, tgt.data_ptr(), tstride, None,
-              loss.data_ptr(), ws.data_ptr(), ws.numel(), _stream())
+              loss.data_ptr(), ws.data_ptr(), ws_bytes, _stream())
     return loss
 
 
@@ -288,31 +339,38 @@ def render_l2(volume: Volume, poses: torch.Tensor, det: Detector, target: torch.
     pose, and with ``grad`` its pose gradient [n, 7]; returns
     (loss, grad_pose or None[, image])."""
     p = _poses(poses)
+    _check_volume(volume, p)
     tgt = _dev_f32(target, "target")
     n = p.shape[0]
     hw = det.pixels
-    tstride = 0 if tgt.numel() == hw else hw
+    tstride = target_stride(tgt.numel(), n, hw)
+    _same_device(p.device, ("target", tgt))
     loss = torch.empty((n,), dtype=torch.float32, device=p.device)
     g = torch.empty((n, 7), dtype=torch.float32, device=p.device) if grad else None
     img = torch.empty((n, det.height, det.width), dtype=torch.float32,
                       device=p.device) if return_image else None
     need = _lib.load().drr_l2_workspace_bytes(ctypes.byref(det.desc), n)
-    ws = workspace if workspace is not None and workspace.numel() >= need else _workspace(
-        need, p.device)
+    ws, ws_bytes = _reuse_workspace(workspace, need, p.device)
     _lib.call("drr_render_l2", volume.packed.data_ptr(), ctypes.byref(volume.desc),
               ctypes.byref(det.desc), p.data_ptr(), n, tgt.data_ptr(), tstride,
               img.data_ptr() if img is not None else None, loss.data_ptr(),
-              g.data_ptr() if g is not None else None, ws.data_ptr(), ws.numel(), _stream())
+              g.data_ptr() if g is not None else None, ws.data_ptr(), ws_bytes, _stream())
     return (loss, g, img) if return_image else (loss, g)
 
 
 def momentum_step(poses: torch.Tensor, velocity: torch.Tensor, grad: torch.Tensor,
                   rate: torch.Tensor, momentum: float) -> None:
     """In place: velocity = momentum * velocity + grad; poses -= rate * velocity."""
+    if poses.ndim != 2 or poses.shape[1] != 7:
+        raise ValueError(f"poses must be [n, 7], got {tuple(poses.shape)}")
     for t, name in ((poses, "poses"), (velocity, "velocity"), (grad, "grad"), (rate, "rate")):
         if not t.is_contiguous():
             raise ValueError(f"{name} must be contiguous")
         _dev_f32(t, name)
+        if t.shape != poses.shape:
+            raise ValueError(f"{name} must have the shape of poses {tuple(poses.shape)}, "
+                             f"got {tuple(t.shape)}")
+        _same_device(poses.device, (name, t))
     n = poses.shape[0]
     _lib.call("drr_pose_momentum_step", poses.data_ptr(), velocity.data_ptr(), grad.data_ptr(),
               rate.data_ptr(), float(momentum), n, _stream())

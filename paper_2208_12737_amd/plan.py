@@ -77,6 +77,10 @@ def _items_array(items: Sequence[Item]):
             _check(k, "image", it.image, it.det.pixels)
         elif it.target is None:
             raise ValueError(f"item {k}: image is required")
+        if it.jac is not None:
+            _check(k, "jac", it.jac, 7 * it.det.pixels)
+        if it.counts is not None:
+            _check(k, "counts", it.counts, it.det.pixels, torch.int32)
         if it.target is not None:
             _check(k, "target", it.target, it.det.pixels)
             for name in ("loss", "grad", "partials"):

@@ -25,7 +25,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from .drr import Detector, Volume, _stream, render, drr, ncc_loss, momentum_step
+from .drr import (Detector, Volume, _stream, render, drr, ncc_loss, momentum_step,
+                  target_stride)
 
 # Step sizes of Sec. 3.2 (rotations in rad, translations in mm); SDD fixed.
 PAPER_RATE_ROT = 5.3e-2
@@ -48,17 +49,26 @@ class BatchedRegistration:
     targets: [n, H, W] fixed images; init: [n, 7] starting poses;
     rates: [n, 7] per-problem, per-parameter step sizes; chains: number of
     independent problem groups (two measured fastest for 32 problems of
-    256 x 256 pixels: one group's launch tail overlaps the other's work)."""
+    256 x 256 pixels: one group's launch tail overlaps the other's work);
+    record: keep every step's poses and pose gradients (eager runs only) in
+    ``pose_history`` / ``grad_history`` [steps + 1, n, 7]."""
 
     def __init__(self, volume: Volume, det: Detector, targets: torch.Tensor,
                  init: torch.Tensor, rates: torch.Tensor, steps: int = 200,
-                 momentum: float = PAPER_MOMENTUM, use_graph: bool = True, chains: int = 2):
+                 momentum: float = PAPER_MOMENTUM, use_graph: bool = True, chains: int = 2,
+                 record: bool = False):
         self.volume, self.det = volume, det
         self.n = init.shape[0]
         self.steps = steps
         self.momentum = float(momentum)
         dev = init.device
-        self.targets = targets.contiguous().to(torch.float32)
+        if init.ndim != 2 or init.shape[1] != 7:
+            raise ValueError(f"init must be [n, 7], got {tuple(init.shape)}")
+        if tuple(rates.shape) != tuple(init.shape):
+            raise ValueError(f"rates must be [n, 7] like init, got {tuple(rates.shape)}")
+        # one target per problem, or one shared by all (stride 0)
+        self.target_stride = target_stride(targets.numel(), self.n, det.pixels)
+        self.targets = targets.contiguous().to(device=dev, dtype=torch.float32)
         self.init = init.detach().clone().contiguous()
         self.rates = rates.contiguous().to(torch.float32)
         self.poses = self.init.clone()
@@ -66,6 +76,14 @@ class BatchedRegistration:
         self.loss = torch.empty((self.n,), dtype=torch.float32, device=dev)   # warm-up only
         self.grad = torch.empty((self.n, 7), dtype=torch.float32, device=dev)
         self.history = torch.empty((steps + 1, self.n), dtype=torch.float32, device=dev)
+        if record and use_graph:
+            raise ValueError("record=True needs use_graph=False (the graph holds only the "
+                             "library's kernels)")
+        self.record = record
+        if record:
+            self.pose_history = torch.empty((steps + 1, self.n, 7), dtype=torch.float32,
+                                            device=dev)
+            self.grad_history = torch.empty_like(self.pose_history)
         self.use_graph = use_graph
         self.graph = None
         # problem ranges of the chains, and one workspace per chain
@@ -83,8 +101,9 @@ class BatchedRegistration:
         ws = self.ws[g]
         _lib.call("drr_render_ncc_grad", self.volume.packed.data_ptr(),
                   ctypes.byref(self.volume.desc), ctypes.byref(self.det.desc),
-                  self.poses[a:b].data_ptr(), b - a, self.targets[a:b].data_ptr(),
-                  self.det.pixels, None, loss_out[a:b].data_ptr(), self.grad[a:b].data_ptr(),
+                  self.poses[a:b].data_ptr(), b - a,
+                  self.targets.data_ptr() + 4 * a * self.target_stride,
+                  self.target_stride, None, loss_out[a:b].data_ptr(), self.grad[a:b].data_ptr(),
                   ws.data_ptr(), ws.numel(), _stream())
 
     def _update(self, g: int):
@@ -93,13 +112,21 @@ class BatchedRegistration:
                   self.grad[a:b].data_ptr(), self.rates[a:b].data_ptr(), self.momentum, b - a,
                   _stream())
 
+    def _keep(self, g: int, i: int):
+        if self.record:
+            a, b = self.groups[g]
+            self.pose_history[i, a:b].copy_(self.poses[a:b])
+            self.grad_history[i, a:b].copy_(self.grad[a:b])
+
     def _chain(self, g: int):
         # the loss of step i is written straight into history row i: the
         # graph holds only the library's kernels (no copy or fill nodes)
         for i in range(self.steps):
             self._objective(g, self.history[i])
+            self._keep(g, i)
             self._update(g)
         self._objective(g, self.history[self.steps])
+        self._keep(g, self.steps)
 
     def _all_steps(self):
         if not self.streams:
