@@ -16,7 +16,8 @@ import torch
 
 import oracle
 from synth import make_phantom, random_poses
-from tests._parity import assert_image_close, column_errors
+from tests._parity import (assert_gradient_close, assert_image_close, column_errors,
+                           oracle_image)
 
 pytestmark = pytest.mark.gpu
 
@@ -46,7 +47,7 @@ def batch():
     off[:, :3] = rng.uniform(-math.radians(15), math.radians(15), (64, 3))
     off[:, 3:6] = rng.uniform(-25.0, 25.0, (64, 3))
     poses = (gt[None] + off).astype(np.float32)
-    target = P.render(vol, torch.from_numpy(gt[None].astype(np.float32)).to(DEV), det)[0]
+    target = torch.from_numpy(oracle_image(grid, gt, H, W, PITCH, PITCH, nthreads=16)).to(DEV)
     pt = torch.from_numpy(poses).to(DEV)
     loss, grad, img = P.render_ncc_grad(vol, pt, det, target, return_image=True)
     _, jac = P.render(vol, pt, det, jacobian=True)
@@ -66,8 +67,11 @@ def test_sampled_poses_match_oracle_image_and_jacobian(batch, b):
     z, gz = oracle.zncc_grad(rimg[0], T)
     assert loss[b].item() == pytest.approx(-z, abs=2e-6)
     ref = -np.einsum("hw,hwj->j", gz, rjac[0])
-    scale = np.abs(gz).sum() * np.abs(rjac[0]).max(axis=(0, 1))
-    assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (grad[b], ref)
+    assert_gradient_close(grad[b].cpu().numpy(), ref, gz, rjac[0], f"fused -ZNCC, pose {b}")
+    # retraced backward of the same image gradient
+    gr = P.render_backward_retrace(vol, torch.from_numpy(poses[b:b + 1]).to(DEV), det,
+                                   torch.from_numpy((-gz).astype(np.float32)).to(DEV)[None])
+    assert_gradient_close(gr[0].cpu().numpy(), ref, gz, rjac[0], f"retrace, pose {b}")
 
 
 @pytest.mark.parametrize("b", [12, 40])
@@ -84,8 +88,7 @@ def test_fused_l2_at_clinical_size(batch, b):
     v, gi = oracle.l2_grad(rimg[0], T)
     assert l2[b].item() == pytest.approx(v, rel=1e-5)
     ref = np.einsum("hw,hwj->j", gi, rjac[0])
-    scale = np.abs(gi).sum() * np.abs(rjac[0]).max(axis=(0, 1))
-    assert np.all(np.abs(g2[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (g2[b], ref)
+    assert_gradient_close(g2[b].cpu().numpy(), ref, gi, rjac[0], f"fused L2, pose {b}")
 
 
 def test_detector_jacobian_at_clinical_size(batch):
@@ -114,15 +117,16 @@ def test_batch_gradient_equals_unfused_path(batch):
         torch.testing.assert_close(pt.grad[b], grad[b], rtol=1e-4, atol=tol)
 
 
-def test_masked_gradient_vs_central_differences(batch):
+@pytest.mark.parametrize("b", [9, 33, 58])
+def test_masked_gradient_vs_central_differences(batch, b):
     """At this size a 1e-4 rad rotation reorders some plane crossings of
-    most rays (only ~0.4-2 % of pixels stay kink-free for the angles, ~17-52 %
-    for the shifts), so both checks run on the kink-free pixels of each
-    parameter: the per-pixel Jacobian against the oracle's difference
+    most rays (only ~0.04-2 % of pixels stay kink-free for the angles,
+    ~17-52 % for the shifts), so both checks run on the kink-free pixels of
+    each parameter: the per-pixel Jacobian against the oracle's difference
     quotients, and the gradient of the masked loss against its difference
-    quotient."""
+    quotient.  At least 10 pixels must be kink-free (a rotation about the
+    principal axis leaves as few as ~15 of the 40 000 for some poses)."""
     P, vol, grid, det, gt, poses, target, loss, grad, img, jac = batch
-    b = 9
     pose = poses[b].astype(np.float64)
     J = jac[b].cpu().numpy().astype(np.float64)
     T = target.cpu().numpy().astype(np.float64)
@@ -135,7 +139,7 @@ def test_masked_gradient_vs_central_differences(batch):
         Ip, _, hp = oracle.render(grid, pp, H, W, PITCH, PITCH, nthreads=8)
         Im, _, hm = oracle.render(grid, pm, H, W, PITCH, PITCH, nthreads=8)
         m = ((hp == h0) & (hm == h0))[0]
-        assert m.sum() >= 100, (j, int(m.sum()))
+        assert m.sum() >= 10, (j, int(m.sum()))
         fdpix = (Ip[0] - Im[0])[m] / (pp[j] - pm[j])
         colscale = np.abs(J[:, :, j]).max()
         assert np.abs(J[:, :, j][m] - fdpix).max() <= FD_RTOL * colscale, j
@@ -167,6 +171,10 @@ def test_fused_gradient_in_the_benchmark_configuration():
     off[:, 6] = 0.0
     moving_np = gt_np + off
     targets = P.render(vol, torch.from_numpy(gt_np).to(DEV), det)
+    # the sampled poses' targets come from the oracle (they are oracle inputs)
+    for b in (31, 200):
+        targets[b] = torch.from_numpy(oracle_image(grid, gt_np[b], 256, 256, 1.4, 1.4,
+                                                   nthreads=16)).to(DEV)
     moving = torch.from_numpy(moving_np).to(DEV)
     ws = torch.empty(_lib.load().drr_ncc_grad_workspace_bytes(ctypes.byref(det.desc), nb),
                      dtype=torch.uint8, device=DEV)
@@ -180,5 +188,4 @@ def test_fused_gradient_in_the_benchmark_configuration():
         z, gz = oracle.zncc_grad(rimg[0], T)
         assert loss[b].item() == pytest.approx(-z, abs=2e-6)
         ref = -np.einsum("hw,hwj->j", gz, rjac[0])
-        scale = np.abs(gz).sum() * np.abs(rjac[0]).max(axis=(0, 1))
-        assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (b, grad[b], ref)
+        assert_gradient_close(grad[b].cpu().numpy(), ref, gz, rjac[0], f"fused -ZNCC, pose {b}")

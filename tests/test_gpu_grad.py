@@ -13,7 +13,8 @@ import torch
 
 import oracle
 from synth import make_phantom, random_poses
-from tests._parity import assert_image_close, column_errors
+from tests._parity import (assert_gradient_close, assert_image_close, column_errors,
+                           oracle_image)
 
 pytestmark = pytest.mark.gpu
 
@@ -153,9 +154,9 @@ def test_backward_stored_and_retrace(small):
     _, rjac = oracle.render_jacobian(grid, poses.astype(np.float64), 40, 44, 2.0, 2.0,
                                      nthreads=4)
     ref = np.einsum("bhw,bhwj->bj", g.astype(np.float64), rjac)
-    scale = np.abs(rjac).max(axis=(1, 2)) * np.abs(g).sum(axis=(1, 2))[:, None]
-    assert np.all(np.abs(gp - ref) <= JAC_RTOL * scale)
-    assert np.all(np.abs(gr - ref) <= JAC_RTOL * scale)
+    for b in range(3):
+        assert_gradient_close(gp[b], ref[b], g[b], rjac[b], f"stored-J backward, pose {b}")
+        assert_gradient_close(gr[b], ref[b], g[b], rjac[b], f"retrace backward, pose {b}")
     np.testing.assert_allclose(gp, gr, rtol=1e-5, atol=1e-6 * np.abs(gp).max())
 
 
@@ -202,7 +203,7 @@ def test_fused_ncc_gradient_matches_oracle(small):
     det = P.Detector(40, 40, 3.0, 3.0)
     gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=8)
     moving = random_poses(3, math.pi / 8, 10.0, 1000.0, seed=9)
-    target = P.render(vol, _gpu(gt), det)
+    target = _gpu(oracle_image(grid, gt[0], 40, 40, 3.0, 3.0))[None]
     loss, grad, img = P.render_ncc_grad(vol, _gpu(moving), det, target[0], return_image=True)
     T = target.cpu().numpy()[0].astype(np.float64)
     rimg, rjac = oracle.render_jacobian(grid, moving.astype(np.float64), 40, 40, 3.0, 3.0,
@@ -212,8 +213,7 @@ def test_fused_ncc_gradient_matches_oracle(small):
         z, gz = oracle.zncc_grad(rimg[b], T)
         assert loss[b].item() == pytest.approx(-z, abs=2e-6)
         ref = -np.einsum("hw,hwj->j", gz, rjac[b])
-        scale = np.abs(gz).sum() * np.abs(rjac[b]).max(axis=(0, 1))
-        assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (b, grad[b], ref)
+        assert_gradient_close(grad[b].cpu().numpy(), ref, gz, rjac[b], f"fused -ZNCC, pose {b}")
     # the fused path equals render -> ncc_loss -> autograd
     p = _gpu(moving).requires_grad_(True)
     l2 = P.ncc_loss(P.drr(vol, p, det), target[0])
@@ -233,7 +233,7 @@ def test_fused_l2_matches_oracle(small):
     det = P.Detector(H, W, 3.0, 3.0)
     gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=18)
     moving = random_poses(4, math.pi / 8, 10.0, 1000.0, seed=19)
-    target = P.render(vol, _gpu(gt), det)
+    target = _gpu(oracle_image(grid, gt[0], H, W, 3.0, 3.0))[None]
     loss, grad, img = P.render_l2(vol, _gpu(moving), det, target[0], return_image=True)
     T = target.cpu().numpy()[0].astype(np.float64)
     rimg, rjac = oracle.render_jacobian(grid, moving.astype(np.float64), H, W, 3.0, 3.0,
@@ -243,8 +243,7 @@ def test_fused_l2_matches_oracle(small):
         v, gl = oracle.l2_grad(rimg[b], T)
         assert loss[b].item() == pytest.approx(v, rel=1e-5)
         ref = np.einsum("hw,hwj->j", gl, rjac[b])
-        scale = np.abs(gl).sum() * np.abs(rjac[b]).max(axis=(0, 1))
-        assert np.all(np.abs(grad[b].cpu().numpy() - ref) <= JAC_RTOL * scale), (b, grad[b], ref)
+        assert_gradient_close(grad[b].cpu().numpy(), ref, gl, rjac[b], f"fused L2, pose {b}")
     only, none = P.render_l2(vol, _gpu(moving), det, target[0], grad=False)
     assert none is None
     torch.testing.assert_close(only, loss, rtol=1e-6, atol=0.0)
@@ -256,10 +255,11 @@ def test_fused_l2_matches_oracle(small):
     gimg = (2.0 / (H * W)) * (img - target[0])
     g2 = P.render_backward_retrace(vol, _gpu(moving), det, gimg)
     torch.testing.assert_close(g2, grad, rtol=1e-4, atol=1e-4 * grad.abs().max().item())
-    # at the target pose the loss and gradient vanish (up to FP32 image rounding)
+    # at the target pose the loss and gradient vanish, up to the difference
+    # of the GPU's and the oracle's image (within the image tolerance)
     l0, g0 = P.render_l2(vol, _gpu(gt), det, target[0])
-    assert l0.item() <= 1e-12 * float((target[0].double() ** 2).mean())
-    assert g0.abs().max().item() <= 1e-5 * grad.abs().max().item()
+    assert l0.item() <= 1e-10 * float((target[0].double() ** 2).mean())
+    assert g0.abs().max().item() <= 1e-4 * grad.abs().max().item()
 
 
 def test_occupancy_settings_give_identical_results(small):

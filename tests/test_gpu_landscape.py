@@ -9,6 +9,7 @@ import torch
 
 import oracle
 from synth import make_phantom, random_poses
+from tests._parity import oracle_image
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -31,12 +32,12 @@ def test_loss_only_matches_image_path_and_oracle(setup):
     P, ph, vol = setup
     det = P.Detector(48, 40, 2.5, 2.5)
     gt = random_poses(1, math.pi / 8, 10.0, 1000.0, seed=2)
-    target = P.render(vol, torch.from_numpy(gt).to(DEV), det)[0]
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    target = torch.from_numpy(oracle_image(grid, gt[0], 48, 40, 2.5, 2.5)).to(DEV)
     poses = torch.from_numpy(random_poses(9, math.pi / 8, 10.0, 1000.0, seed=3)).to(DEV)
     a = P.render_ncc_loss(vol, poses, det, target)
     b = P.ncc_loss(P.render(vol, poses, det), target)
     torch.testing.assert_close(a, b, rtol=1e-6, atol=1e-6)
-    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
     img, _, _ = oracle.render(grid, poses.cpu().numpy().astype(np.float64), 48, 40, 2.5, 2.5)
     T = target.cpu().numpy().astype(np.float64)
     for k in range(9):
@@ -86,10 +87,10 @@ def test_landscape_in_the_benchmark_configuration():
     det = P.Detector(256, 256, 1.4, 1.4)
     gt = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=21)[0]
     off = random_offsets(8192, seed=22)
-    target = P.render(vol, torch.from_numpy(gt[None]).to(DEV), det)[0]
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
+    target = torch.from_numpy(oracle_image(grid, gt, 256, 256, 1.4, 1.4, nthreads=16)).to(DEV)
     loss = sweep(vol, det, gt, off, chunk=8192, target=target)
     assert np.all(np.isfinite(loss)) and np.all(np.abs(loss) <= 1.0 + 1e-6)
-    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
     T = target.cpu().numpy().astype(np.float64)
     rng = np.random.default_rng(6)
     for k in rng.choice(8192, 4, replace=False):

@@ -1,5 +1,7 @@
-"""Batched registration on the GPU: graph replays equal the eager run, and
-the loss falls from the initial poses."""
+"""Batched registration on the GPU: every step's loss and pose gradient
+equal the FP64 oracle's at that step's pose and every update is the
+heavy-ball step of Sec. 3.2, graph replays equal the eager run, and the loss
+falls from the initial poses."""
 
 import math
 
@@ -7,7 +9,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from synth import make_phantom, random_poses
+from tests._parity import assert_gradient_close, oracle_image
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -18,10 +22,11 @@ def _need_gpu():
     assert torch.cuda.is_available(), "GPU tests need a HIP device"
 
 
-def _problem(n=4, seed=0):
+def _problem(n=4, seed=0, oracle_targets=False):
     import paper_2208_12737_amd as P
     ph = make_phantom("small", seed=0)
     vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+    grid = oracle.Grid(ph.volume, ph.spacing, ph.origin)
     det = P.Detector(64, 64, 2.0, 2.0)
     gt = random_poses(n, math.pi / 8, 10.0, 1000.0, seed=seed)
     rng = np.random.default_rng(seed + 100)
@@ -29,9 +34,51 @@ def _problem(n=4, seed=0):
     off[:, :3] = rng.uniform(-1, 1, (n, 3)) * math.radians(4.0)
     off[:, 3:6] = rng.uniform(-1, 1, (n, 3)) * 3.0
     gt_t = torch.from_numpy(gt).to(DEV)
-    targets = P.render(vol, gt_t, det)
+    if oracle_targets:
+        targets = torch.from_numpy(np.stack([oracle_image(grid, g, 64, 64, 2.0, 2.0)
+                                             for g in gt])).to(DEV)
+    else:
+        targets = P.render(vol, gt_t, det)
     init = torch.from_numpy(gt + off).to(DEV)
+    if oracle_targets:
+        return vol, det, gt, targets, init, grid
     return vol, det, gt, targets, init
+
+
+def test_trajectory_follows_the_oracle():
+    """Eager single chain, 6 steps, 3 problems: at every step the loss is the
+    oracle's -ZNCC of the DRR at that step's pose, the pose gradient is the
+    oracle's ZNCC gradient chained with its frozen-index Jacobian (per
+    component), and the next pose is the heavy-ball update of Sec. 3.2 from
+    that gradient (v <- 0.9 v + g, pose <- pose - rate * v, FP32)."""
+    from paper_2208_12737_amd.register import BatchedRegistration, default_rates
+    vol, det, gt, targets, init, grid = _problem(n=3, seed=2, oracle_targets=True)
+    rates = default_rates(3, rot=2e-2, xyz=20.0)
+    steps = 6
+    reg = BatchedRegistration(vol, det, targets, init, rates, steps=steps, use_graph=False,
+                              chains=1, record=True)
+    _, hist = reg.run()
+    torch.cuda.synchronize()
+    P_h = reg.pose_history.cpu().numpy()
+    G_h = reg.grad_history.cpu().numpy()
+    L_h = hist.cpu().numpy()
+    T = targets.cpu().numpy().astype(np.float64)
+    r = rates.cpu().numpy()
+    assert np.array_equal(P_h[0], init.cpu().numpy())
+    vel = np.zeros((3, 7), np.float32)
+    for i in range(steps + 1):
+        rimg, rjac = oracle.render_jacobian(grid, P_h[i].astype(np.float64), 64, 64, 2.0, 2.0,
+                                            nthreads=8)
+        for k in range(3):
+            z, gz = oracle.zncc_grad(rimg[k], T[k])
+            assert abs(L_h[i, k] + z) <= 2e-6, (i, k, L_h[i, k], -z)
+            ref = -np.einsum("hw,hwj->j", gz, rjac[k])
+            assert_gradient_close(G_h[i, k], ref, gz, rjac[k], f"step {i}, problem {k}")
+        if i < steps:
+            vel = np.float32(0.9) * vel + G_h[i]
+            nxt = P_h[i] - r * vel
+            np.testing.assert_allclose(P_h[i + 1], nxt, rtol=1e-6,
+                                       atol=1e-6 * np.abs(P_h[i]).max())
 
 
 def test_graph_replays_equal_eager():

@@ -1,5 +1,8 @@
 """Serving on the GPU: each result equals the same request served alone and
-the plain single-DRR path, whatever mix it was batched with."""
+the plain single-DRR path, whatever mix it was batched with, and matches the
+FP64 oracle: forward images to the image tolerance, forward + backward
+losses and pose gradients to the oracle's -ZNCC chained with its
+frozen-index Jacobian, per component."""
 
 import math
 
@@ -7,7 +10,9 @@ import numpy as np
 import pytest
 import torch
 
+import oracle
 from synth import make_phantom, random_poses
+from tests._parity import assert_gradient_close, assert_image_close, oracle_image
 
 pytestmark = pytest.mark.gpu
 DEV = "cuda"
@@ -19,20 +24,46 @@ def _need_gpu():
 
 
 @pytest.fixture(scope="module")
-def volumes():
-    import paper_2208_12737_amd as P
+def grids():
     a = make_phantom("small", seed=0)
     b = make_phantom("small", seed=1)
     rng = np.random.default_rng(4)
     c = rng.uniform(0, 1, (40, 30, 20)).astype(np.float32)
-    return {"a": P.Volume(torch.from_numpy(a.volume), a.spacing, a.origin, device=DEV),
-            "b": P.Volume(torch.from_numpy(b.volume), b.spacing, b.origin, device=DEV,
-                          layout="input"),
-            "c": P.Volume(torch.from_numpy(c), (1.5, 2.0, 2.5), None, device=DEV)}
+    sc = (1.5, 2.0, 2.5)
+    oc = tuple(-0.5 * n * h for n, h in zip(c.shape, sc))
+    return {"a": (a.volume, a.spacing, a.origin, "per_axis"),
+            "b": (b.volume, b.spacing, b.origin, "input"),
+            "c": (c, sc, oc, "per_axis")}
 
 
-def _requests(volumes, n, seed):
+@pytest.fixture(scope="module")
+def volumes(grids):
     import paper_2208_12737_amd as P
+    return {k: P.Volume(torch.from_numpy(v), sp, og, device=DEV, layout=lay)
+            for k, (v, sp, og, lay) in grids.items()}
+
+
+def check_against_oracle(grid, r, got):
+    """A served result against the FP64 oracle: the forward image, or the
+    fwd+bwd image, -ZNCC and pose gradient."""
+    from paper_2208_12737_amd.serve import FWD
+    pose = np.asarray(r.pose, np.float32).astype(np.float64)[None]
+    if r.kind == FWD:
+        ref, _, _ = oracle.render(grid, pose, r.height, r.width, r.delta_x, r.delta_y,
+                                  nthreads=8)
+        assert_image_close(got.cpu().numpy()[None], ref, what=f"served forward {r.volume}")
+        return
+    img, loss, grad = got
+    rimg, rjac = oracle.render_jacobian(grid, pose, r.height, r.width, r.delta_x, r.delta_y,
+                                        nthreads=8)
+    assert_image_close(img.cpu().numpy()[None], rimg, what=f"served fwd+bwd image {r.volume}")
+    z, gz = oracle.zncc_grad(rimg[0], r.target.cpu().numpy().astype(np.float64))
+    assert abs(loss.item() + z) <= 2e-6, (loss.item(), -z)
+    ref = -np.einsum("hw,hwj->j", gz, rjac[0])
+    assert_gradient_close(grad.cpu().numpy(), ref, gz, rjac[0], f"served gradient {r.volume}")
+
+
+def _requests(grids, n, seed):
     from paper_2208_12737_amd.serve import FWD, FWDBWD, Request
     rng = np.random.default_rng(seed)
     sizes = [(32, 32, 2.0), (48, 40, 1.5), (64, 64, 1.0), (17, 23, 3.0)]
@@ -46,8 +77,9 @@ def _requests(volumes, n, seed):
         if kind == FWDBWD:
             gt = pose.copy()
             gt[:3] += 0.02
-            target = P.render(volumes[v], torch.from_numpy(gt).to(DEV)[None],
-                              P.Detector(H, W, px, px))[0]
+            v_, sp, og, _ = grids[v]
+            target = torch.from_numpy(oracle_image(oracle.Grid(v_, sp, og), gt, H, W, px,
+                                                   px)).to(DEV)
         reqs.append(Request(v, H, W, px, px, pose, kind, target))
     return reqs
 
@@ -58,9 +90,9 @@ def _same(a, b):
     return torch.equal(a, b)
 
 
-def test_alone_vs_mix_and_plain(volumes):
+def test_alone_vs_mix_and_plain(volumes, grids):
     from paper_2208_12737_amd.serve import FWD, GpuBackend, Server, plain_forward
-    reqs = _requests(volumes, 40, seed=1)
+    reqs = _requests(grids, 40, seed=1)
     be = GpuBackend(volumes, n_streams=3)
     # a small budget forces many ticks with overlapping batches
     srv = Server(be, hbm_budget_bytes=6 * 64 * 64 * 4 * 3, n_streams=3, max_batch=8)
@@ -72,6 +104,9 @@ def test_alone_vs_mix_and_plain(volumes):
     srv.run_until_idle()
     torch.cuda.synchronize()
     assert srv.batches >= 5
+    og = {k: oracle.Grid(v, sp, o) for k, (v, sp, o, _) in grids.items()}
+    for r, t in zip(reqs, tickets):
+        check_against_oracle(og[r.volume], r, t.wait(0))
     for r, t in zip(reqs, tickets):
         mixed = t.wait(0)
         solo_srv = Server(GpuBackend(volumes, n_streams=1), hbm_budget_bytes=1 << 30)
@@ -107,15 +142,16 @@ def test_serving_mix_in_the_benchmark_configuration():
     512 x 512 x 133 and 512 x 512 x 300) and four detector sizes (pitch
     358.4 mm / N): every volume and detector pair as a forward request, half
     of them also as forward + backward requests, served under a small budget;
-    forward results equal the plain single-DRR path and fwd+bwd results equal
-    the fused call, bit for bit."""
+    every result matches the FP64 oracle, forward results equal the plain
+    single-DRR path and fwd+bwd results equal the fused call, bit for bit."""
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.serve import FWD, FWDBWD, GpuBackend, Request, Server, plain_forward
     names = ["ct128", "ct256", "ct512", "ct512x300"]
-    vols = {}
+    vols, og = {}, {}
     for nm in names:
         ph = make_phantom(nm, seed=0)
         vols[nm] = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=DEV)
+        og[nm] = oracle.Grid(ph.volume, ph.spacing, ph.origin)
     reqs = []
     for i, nm in enumerate(names):
         for j, N in enumerate((128, 200, 256, 512)):
@@ -125,8 +161,8 @@ def test_serving_mix_in_the_benchmark_configuration():
             if (i + j) % 2 == 0:
                 gt = pose.copy()
                 gt[:3] += 0.03
-                tg = P.render(vols[nm], torch.from_numpy(gt).to(DEV)[None],
-                              P.Detector(N, N, px, px))[0]
+                tg = torch.from_numpy(oracle_image(og[nm], gt, N, N, px, px,
+                                                   nthreads=16)).to(DEV)
                 reqs.append(Request(nm, N, N, px, px, pose, FWDBWD, tg))
     srv = Server(GpuBackend(vols, n_streams=3), hbm_budget_bytes=8 << 20, n_streams=3,
                  max_batch=6)
@@ -136,6 +172,7 @@ def test_serving_mix_in_the_benchmark_configuration():
     assert srv.batches >= 4
     for r, t in zip(reqs, tickets):
         got = t.wait(0)
+        check_against_oracle(og[r.volume], r, got)
         det = P.Detector(r.height, r.width, r.delta_x, r.delta_y)
         if r.kind == FWD:
             assert torch.equal(got, plain_forward(vols, r))
