@@ -25,7 +25,8 @@
  *  - No call allocates device memory except drr_plan_create.  Calls that need
  *    scratch memory take a caller-provided device workspace and report its
  *    required size through a *_workspace_bytes query; too small a workspace
- *    gives DRR_ENOMEM and enqueues nothing.
+ *    gives DRR_ENOMEM and enqueues nothing.  drr_render_ncc_grad_noalloc
+ *    uses a fixed device array of the library instead.
  *  - Results are deterministic: per-pose reductions use a fixed order, so the
  *    same inputs give bitwise the same outputs, independent of batch size,
  *    batch composition and of which other work shares the GPU.
@@ -194,6 +195,26 @@ int32_t drr_render_ncc_grad(const void* packed, const drr_volume_desc* vol,
                             const float* target, int64_t target_stride, float* image,
                             float* loss, float* grad_pose, void* workspace,
                             size_t workspace_bytes, void* stream);
+
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid allocation): the same
+ * fused objective as drr_render_ncc_grad, with the same arguments and
+ * results (bitwise), except that its scratch is a fixed device array of
+ * DRR_NOALLOC_SCRATCH_BYTES inside the library, one per GPU, kept until the
+ * process ends.  The call allocates nothing (no hipMalloc, no library
+ * allocation); its first call on a device only looks up that array's
+ * address.  Batches whose drr_ncc_grad_workspace_bytes(det, n_poses) exceeds
+ * DRR_NOALLOC_SCRATCH_BYTES return DRR_ENOMEM and enqueue nothing (at the
+ * direct launch shape, 256 x 256-pixel poses take 53 248 bytes each, so up
+ * to 157 of them fit).  Every call on one GPU shares that GPU's array: calls
+ * whose work overlaps on the device (other streams, other threads) race and
+ * must be serialized by the caller; a call on one stream after another is
+ * safe.  Nothing in the array needs clearing between calls. */
+#define DRR_NOALLOC_SCRATCH_BYTES (8u << 20)
+int32_t drr_render_ncc_grad_noalloc(const void* packed, const drr_volume_desc* vol,
+                                    const drr_detector_desc* det, const float* poses,
+                                    int32_t n_poses, const float* target, int64_t target_stride,
+                                    float* image, float* loss, float* grad_pose, void* stream);
 
 /* Loss only (no gradient), e.g. for sweeps of the loss landscape (Sec. 3.2):
  * one tracing pass renders each pose and reduces the five ZNCC moments per

@@ -25,6 +25,7 @@ DRR_ITEM_NCC = 4
 DRR_PLAN_PERSISTENT = 0
 DRR_PLAN_FLAT = 1
 DRR_PLAN_AUTO = 2
+DRR_NOALLOC_SCRATCH_BYTES = 8 << 20
 
 
 class DrrError(RuntimeError):
@@ -83,6 +84,7 @@ SIGNATURES = {
     "drr_ncc_backward": (_I32, [_V, _V, _I64, _V, _V, _I32, _I64, _V, _V]),
     "drr_ncc_grad_workspace_bytes": (_SZ, [_DD, _I32]),
     "drr_render_ncc_grad": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _V, _SZ, _V]),
+    "drr_render_ncc_grad_noalloc": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _V]),
     "drr_ncc_loss_workspace_bytes": (_SZ, [_DD, _I32]),
     "drr_render_ncc_loss": (_I32, [_V, _VD, _DD, _V, _I32, _V, _I64, _V, _V, _V, _SZ, _V]),
     "drr_l2_workspace_bytes": (_SZ, [_DD, _I32]),

@@ -5,6 +5,7 @@
 #include <string.h>
 
 #include <atomic>
+#include <mutex>
 
 #include "common.hpp"
 #include "reduce_kernels.hpp"
@@ -95,6 +96,40 @@ static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
 }
 
 static size_t chunks_of(int64_t hw) { return (size_t)((hw + kChunkPixels - 1) / kChunkPixels); }
+
+// Scratch of drr_render_ncc_grad_noalloc: file-scope device memory, one copy
+// on each GPU the library runs on, held until the process ends.  Host code
+// must not pass `scratch` itself to a kernel (on the host it names a
+// stand-in, not a device address): its device address is looked up once per
+// device with hipGetSymbolAddress and kept in g_scratch_ptr.
+static_assert(DRR_NOALLOC_SCRATCH_BYTES % sizeof(double) == 0, "scratch holds doubles");
+static __device__ __align__(256) double scratch[DRR_NOALLOC_SCRATCH_BYTES / sizeof(double)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void* g_scratch_ptr[kMaxDevices];   // device address of `scratch`, per device
+
+// Device address of `scratch` on the current device (looked up on the first
+// call on that device, with the device current).
+static int32_t scratch_on_current_device(void** out)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return fail(DRR_EHIP, "hipGetDevice: %s", hipGetErrorString(e));
+    if (dev < 0 || dev >= kMaxDevices)
+        return fail(DRR_ENOTSUP, "device %d: at most %d devices", dev, kMaxDevices);
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p)
+            return fail(DRR_EHIP, "hipGetSymbolAddress(scratch) on device %d: %s", dev,
+                        hipGetErrorString(e));
+        g_scratch_ptr[dev] = p;
+    }
+    *out = g_scratch_ptr[dev];
+    return DRR_OK;
+}
 
 }  // namespace drr
 
@@ -335,6 +370,26 @@ int32_t drr_render_ncc_grad(const void* packed, const drr_volume_desc* vol,
                        (const double*)workspace, flat_grid(*det).wg_per_pose, (double)hw, loss,
                        grad_pose);
     return check_launch("ncc_grad_finalize");
+}
+
+int32_t drr_render_ncc_grad_noalloc(const void* packed, const drr_volume_desc* vol,
+                                    const drr_detector_desc* det, const float* poses,
+                                    int32_t n_poses, const float* target, int64_t target_stride,
+                                    float* image, float* loss, float* grad_pose, void* stream)
+{
+    int32_t st = common_render_checks(packed, vol, det, poses, n_poses);
+    if (st) return st;
+    if (n_poses == 0) return DRR_OK;
+    const size_t need = drr_ncc_grad_workspace_bytes(det, n_poses);
+    if (need > (size_t)DRR_NOALLOC_SCRATCH_BYTES)
+        return fail(DRR_ENOMEM,
+                    "render_ncc_grad_noalloc: %d poses of %d x %d pixels need %zu bytes of "
+                    "scratch, more than the fixed %zu; split the batch",
+                    n_poses, det->height, det->width, need, (size_t)DRR_NOALLOC_SCRATCH_BYTES);
+    void* ws = nullptr;
+    if ((st = scratch_on_current_device(&ws))) return st;
+    return drr_render_ncc_grad(packed, vol, det, poses, n_poses, target, target_stride, image,
+                               loss, grad_pose, ws, DRR_NOALLOC_SCRATCH_BYTES, stream);
 }
 
 size_t drr_ncc_loss_workspace_bytes(const drr_detector_desc* det, int32_t n_poses)

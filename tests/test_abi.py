@@ -190,3 +190,19 @@ int main(void)
     run = subprocess.run([str(exe)], capture_output=True, text=True, timeout=120)
     assert run.returncode == 0, (run.returncode, run.stderr)
     assert run.stdout.strip() == "ok"
+
+
+def test_noalloc_scratch_limit_matches_header_and_is_checked_on_the_host():
+    src = open(os.path.join(ROOT, "include", "drr.h")).read()
+    m = re.search(r"#define DRR_NOALLOC_SCRATCH_BYTES \((\d+)u << (\d+)\)", src)
+    assert m and int(m.group(1)) << int(m.group(2)) == _lib.DRR_NOALLOC_SCRATCH_BYTES
+    lib = _lib.load()
+    vol = _lib.volume_desc((8, 8, 8), (1, 1, 1), (-4, -4, -4))
+    det = _lib.detector_desc(256, 256, 1.0, 1.0)
+    per_pose = lib.drr_ncc_grad_workspace_bytes(ctypes.byref(det), 1)
+    n = _lib.DRR_NOALLOC_SCRATCH_BYTES // per_pose + 1
+    # rejected before any device work: the pointers are never dereferenced
+    st = lib.drr_render_ncc_grad_noalloc(8, ctypes.byref(vol), ctypes.byref(det), 8, n, 8, 0,
+                                         None, 8, 8, None)
+    assert st == _lib.DRR_ENOMEM
+    assert b"scratch" in lib.drr_last_error()
