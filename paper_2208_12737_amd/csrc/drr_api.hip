@@ -82,10 +82,13 @@ static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
     if (blocks > 0x7FFFFFFFull) return fail(DRR_ENOTSUP, "too many tiles in one launch");
     // launches of up to 16 workgroups per CU (16 poses of 256 x 256 pixels)
     // take the deep pipeline in every mode: measured faster down to a lone
-    // wave per SIMD, where it cuts a single DRR's time by a third
-    const bool small = blocks <= 16ull * (uint64_t)num_cus();
-    auto kernel = small ? render_flat<kTW, kWX, kWY, MODE, kDeepDepth>
-                        : render_flat<kTW, kWX, kWY, MODE, full_depth<MODE>()>;
+    // wave per SIMD, where it cuts a single DRR's time by a third; launches
+    // of at most one workgroup per CU (a single DRR of up to 256 x 256
+    // pixels) leave each SIMD one wave and take the deepest pipeline
+    const uint64_t cus = (uint64_t)num_cus();
+    auto kernel = blocks <= cus ? render_flat<kTW, kWX, kWY, MODE, kTinyDepth>
+                  : blocks <= 16ull * cus ? render_flat<kTW, kWX, kWY, MODE, kDeepDepth>
+                                          : render_flat<kTW, kWX, kWY, MODE, full_depth<MODE>()>;
     hipLaunchKernelGGL(kernel, dim3((unsigned)blocks),
                        dim3(DefaultShape::threads),
                        occupancy_lds(wg_per_cu_for(vol), flat_static_lds<MODE>()), stream,

@@ -30,11 +30,17 @@ constexpr uint32_t kBufferDword3 = 0x00020000u;  // gfx9 raw buffer, 32-bit data
 // always includes every segment.
 constexpr double kSliver = 0x1p-36;
 
-// Deepest gather pipeline (crossings the merge runs ahead of the
-// accumulation; the launches choose 2 or 4).  The depth changes only when
-// loads are issued, never the order of the arithmetic: results are bitwise
-// the same at any depth.
+// Gather pipeline depth (crossings the merge runs ahead of the
+// accumulation) of the small launches, which leave a SIMD with few waves to
+// hide the latency of the gathers.  The depth changes only when loads are
+// issued, never the order of the arithmetic: results are bitwise the same at
+// any depth.
 constexpr int kDeepDepth = 4;
+// Depth of launches that leave each SIMD a single wave.
+#ifndef DRR_TINY_DEPTH
+#define DRR_TINY_DEPTH 6
+#endif
+constexpr int kTinyDepth = DRR_TINY_DEPTH;
 
 // A packed volume: one or three copies of the zero-bordered grid, each in
 // its own memory order.  pitch[q][c] is the byte distance between
@@ -161,7 +167,8 @@ template <bool JAC, bool COUNT, int DERIVED, int DEPTH>
 __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
                                const int32_t pitch[3], const double s[3], const double d[3])
 {
-    static_assert(DEPTH == 1 || DEPTH == 2 || DEPTH == 4, "prefetch depth 1, 2 or 4");
+    static_assert(DEPTH >= 1 && DEPTH <= 12, "gather pipeline depth 1..12");
+    static_assert(DEPTH >= 2 || !JAC, "the Jacobian sums need a pipeline depth of at least 2");
     constexpr int derived = DERIVED;
     RayAcc r;
     r.sum = 0.0;
@@ -235,180 +242,219 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         return x;
     };
     const Axis X0 = axis(0), Y0 = axis(1), Z0 = axis(2);
-    double ax = X0.a, ay = Y0.a, az = Z0.a;
-    const double dax = X0.da, day = Y0.da, daz = Z0.da;
-    const uint32_t sx = X0.stride, sy = Y0.stride, sz = Z0.stride;
+    // The axes by role: e1 < e2 are the two whose Jacobian sums the loop
+    // keeps, `derived` the one whose sums follow from the identities.
+    constexpr int e1 = derived == 0 ? 1 : 0, e2 = derived == 2 ? 1 : 2;
+    const Axis& E1 = e1 == 0 ? X0 : Y0;
+    const Axis& E2 = e2 == 2 ? Z0 : Y0;
+    const Axis& ED = derived == 0 ? X0 : (derived == 1 ? Y0 : Z0);
+    double a1 = E1.a, a2 = E2.a, ad = ED.a;
+    // Each axis advances by fma(f, 128 da, a) with the factor f = 2^-7 for
+    // the axis that advances and 0 for the others: f * 128 da = da exactly,
+    // so this is a + da rounded once.  The high word of f = 2^-7 is
+    // 0x3F800000, the bit pattern of 1.0f, so the factor's high word read as
+    // a float is the 0/1 weight that files a crossing under its axis in the
+    // Jacobian sums (one select per axis serves both).
+    // (Steps beyond 2^1000 in alpha, from a direction component of the
+    // order of 1e-300, are clamped there so that 128 da stays finite; such
+    // an axis is never crossed twice within the ray's [0, 1].)
+    const double d1 = fmin(E1.da, 0x1p1000) * 128.0, d2 = fmin(E2.da, 0x1p1000) * 128.0,
+                 dd = fmin(ED.da, 0x1p1000) * 128.0;
+    const uint32_t s1 = E1.stride, s2 = E2.stride, sd = ED.stride;
+    // With the Jacobian, the step factors (2^-7 or 0, low words always 0) of
+    // axes e1 and e2 rotate with the in-flight registers (they are the
+    // weights the accumulation needs DEPTH steps later); fd is the derived
+    // axis's.
+    double fd = 0.0;
     uint32_t off = X0.off + Y0.off + Z0.off;
     const uint32_t off_entry = off;
     double acc = 0.0;
     int32_t nseg = 0;
     float vprev = 0.0f;
-    // sums of the two explicitly accumulated axes e1 < e2 (all but `derived`)
-    constexpr int e1 = derived == 0 ? 1 : 0, e2 = derived == 2 ? 1 : 2;
-    float A1s = 0.f, A2s = 0.f, B1s = 0.f, B2s = 0.f;
+    // e1 and e2 sums: the running sum A of the jumps at the axis's
+    // crossings, and the sum R of A after each of them (B = sum alpha *
+    // jump follows from A and R, see below)
+    float A1s = 0.f, A2s = 0.f, R1s = 0.f, R2s = 0.f;
+    // The traversal clips at the double just below alpha_max: a plane of e1
+    // or e2 that the repeated additions land exactly on alpha_max is then
+    // not taken at the exit (no merge step ever picks it), so the crossings
+    // those axes advance over are the same whatever the pipeline depth.
+    // The last segment is one ulp of alpha short (a relative change of
+    // about 1e-16 of the path sum).
+    const double amax_m = __longlong_as_double(__double_as_longlong(amax) - 1);
 
     // The traversal is split into a merge (pick the next crossing, advance
     // that axis, issue the gather of the voxel beyond it) and an accumulation
     // (add a closed segment's length x value).  The merge runs DEPTH
     // crossings ahead of the accumulation, so every gather has DEPTH merge
-    // steps of independent work between its issue and its use.  Register
-    // names rotate through an unrolled loop instead of being copied: a copy
-    // of a loaded value would force an early wait on the load.
+    // steps of independent work between its issue and its use.  The
+    // in-flight values live in DEPTH + 1 registers whose roles rotate
+    // through a fully unrolled loop (constant indices only): a copy of a
+    // loaded value would force an early wait on the load.
     // (Macros rather than lambdas: a by-reference closure makes the compiler
     // keep the strides on the stack and load them every step.)
     //
-    // Exactly one axis advances per merge (x before y before z).  Tied
-    // crossings are therefore taken one per step, the later ones closing
-    // zero-length segments; the voxel sequence and the sum are unchanged.
-    // Once the next crossing is the exit, every further merge returns the
-    // exit again (z "advances" harmlessly) and closes empty segments.
-    // For the Jacobian each crossing carries 0/1 weights (w1, w2) saying
-    // whether its plane belongs to axis e1 or e2, so that the sums are plain
-    // FMAs.
-#define DRR_MERGE(vn, a_new, w1_new, w2_new)                                     \
+    // Exactly one axis advances per merge (e1 before e2 before the derived
+    // axis).  Tied crossings are therefore taken one per step, the later
+    // ones closing zero-length segments; the voxel sequence and the sum are
+    // unchanged.  Once the next crossing is the clip, every further merge
+    // returns it again (the derived axis "advances" harmlessly, with weight
+    // 0) and closes empty segments.
+#define DRR_MERGE(vn, a_new, f1_new, f2_new)                                     \
     do {                                                                         \
-        const double anext = min_nn(min_nn(ax, ay), min_nn(az, amax));           \
-        const bool bx = ax == anext;                                             \
-        const bool by = !bx && ay == anext;                                      \
-        const bool bz = !bx && !by;                                              \
-        ax = fma(bx ? 1.0 : 0.0, dax, ax);                                       \
-        ay = fma(by ? 1.0 : 0.0, day, ay);                                       \
-        az = fma(bz ? 1.0 : 0.0, daz, az);                                       \
-        off += bx ? sx : (by ? sy : sz);                                         \
+        const double anext = min_nn(min_nn(a1, a2), min_nn(ad, amax_m));         \
+        const bool b1 = a1 == anext;                                             \
+        const bool b2 = !b1 && a2 == anext;                                      \
+        const bool bd = (!b1) != b2;      /* = !b1 && !b2, as b2 implies !b1 */ \
+        if (JAC) {                                                               \
+            /* the factors of axes e1 and e2 are the crossing's weights   */    \
+            f1_new = __hiloint2double(b1 ? 0x3F800000 : 0, __double2loint(f1_new)); \
+            f2_new = __hiloint2double(b2 ? 0x3F800000 : 0, __double2loint(f2_new)); \
+            fd = __hiloint2double(bd ? 0x3F800000 : 0, __double2loint(fd));      \
+            a1 = fma(f1_new, d1, a1);                                            \
+            a2 = fma(f2_new, d2, a2);                                            \
+            ad = fma(fd, dd, ad);                                                \
+        } else {                                                                 \
+            a1 = fma(b1 ? 0x1p-7 : 0.0, d1, a1);                                 \
+            a2 = fma(b2 ? 0x1p-7 : 0.0, d2, a2);                                 \
+            ad = fma(bd ? 0x1p-7 : 0.0, dd, ad);                                 \
+        }                                                                        \
+        off += b1 ? s1 : (b2 ? s2 : sd);                                         \
         vn = ld(rsrc, off);                                                      \
         /* keep the gather where it is: the scheduler would otherwise sink  */ \
         /* it towards its use and shorten the distance the pipeline buys    */ \
         __builtin_amdgcn_sched_barrier(0);                                       \
         a_new = anext;                                                           \
-        if (JAC) {                                                               \
-            const bool b1 = e1 == 0 ? bx : by;                                   \
-            const bool b2 = e2 == 2 ? bz : by;                                   \
-            w1_new = b1 ? 1.0f : 0.0f;                                           \
-            w2_new = b2 ? 1.0f : 0.0f;                                           \
-        }                                                                        \
     } while (0)
     // Closes segment [a_start, a_end] in the voxel of value vc; the crossing
     // at a_start (weights w1, w2) has V_before = vprev and V_after = vc.
-#define DRR_ACCUM(vc, a_start, a_end, w1, w2)                                    \
+    // Crossings at or after the clip change nothing (their jump is 0, and
+    // they are the derived axis's, of weight 0).
+    // Crossing m of an axis lies at alpha = a_first + (m - 1) da, so with the
+    // running sums A_m and R = sum_m A_m over its n crossings,
+    //   sum_m alpha_m jump_m = a_first A_n + da (n A_n - R),
+    // which needs no per-step product with alpha.  (A plane of e1 or e2 that
+    // landed exactly on the clip value would be taken with jump 0: it adds
+    // 1 to n and A_n to R and leaves n A_n - R unchanged.)
+#define DRR_ACCUM(vc, a_start, a_end, f1, f2)                                    \
     do {                                                                         \
         const double seg = (a_end) - (a_start);                                  \
         acc = fma(seg, (double)(vc), acc);                                       \
         if (COUNT) nseg += seg > kSliver ? 1 : 0;                                \
         if (JAC) {                                                               \
-            const bool live = (a_start) < amax;                                  \
-            const float dl = live ? vprev - (vc) : 0.0f;                         \
-            const float tdl = (float)(a_start) * dl;                             \
-            A1s = fmaf((w1), dl, A1s);                                           \
-            B1s = fmaf((w1), tdl, B1s);                                          \
-            A2s = fmaf((w2), dl, A2s);                                           \
-            B2s = fmaf((w2), tdl, B2s);                                          \
-            vprev = live ? (vc) : vprev;                                         \
+            const float w1 = __int_as_float(__double2hiint(f1));                 \
+            const float w2 = __int_as_float(__double2hiint(f2));                 \
+            const float vnew = (a_start) < amax_m ? (vc) : vprev;                \
+            const float dl = vprev - vnew;                                       \
+            A1s = fmaf(w1, dl, A1s);                                             \
+            R1s = fmaf(w1, A1s, R1s);                                            \
+            A2s = fmaf(w2, dl, A2s);                                             \
+            R2s = fmaf(w2, A2s, R2s);                                            \
+            vprev = vnew;                                                        \
         }                                                                        \
     } while (0)
-    const float w1_entry = amin_ax == e1 ? 1.0f : 0.0f;
-    const float w2_entry = amin_ax == e2 ? 1.0f : 0.0f;
 
     // Every crossing either ends the ray or advances an axis by one plane,
     // so n_x + n_y + n_z + 4 steps bound the loop for any input.  The loop
     // is wave-uniform; lanes that finished idle under the exec mask.  All
     // steps of an iteration run for a live lane (steps after the exit close
     // empty segments), which keeps each load ahead of its use.
+    constexpr int NR = DEPTH + 1;   // in-flight registers
+    float v[NR];
+    double a[NR], p[NR], q[NR];     // p, q: step factors of axes e1, e2
+    // (the entry crossing at alpha_min is not one of an axis's loop
+    // crossings: it is added after the loop, and has weight 0 here)
+    v[0] = ld(rsrc, off);
+    a[0] = amin;
+#pragma unroll
+    for (int k = 0; k < NR; ++k) {
+        if (k > 0) {
+            v[k] = 0.0f;
+            a[k] = amin;
+        }
+        p[k] = q[k] = 0.0;
+    }
+#pragma unroll
+    for (int k = 1; k < DEPTH; ++k) DRR_MERGE(v[k], a[k], p[k], q[k]);
+    // iteration: segment k = [a_k, a_{k+1}] is closed while the merge
+    // produces the crossing DEPTH places ahead, into register (k + DEPTH) % NR
+    const int cap = (V.n[0] + V.n[1] + V.n[2] + 3 * DEPTH + 2) / NR;
     bool active = true;
-    if (DEPTH == 1) {
-        float v0 = ld(rsrc, off), v1 = 0.0f;
-        double a0 = amin, a1 = amin;
-        float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f;
-        const int cap = (V.n[0] + V.n[1] + V.n[2] + 5) / 2;
-        for (int it = 0; it < cap; ++it) {
-            if (active) {
-                DRR_MERGE(v1, a1, p1, q1);
-                DRR_ACCUM(v0, a0, a1, p0, q0);
-                DRR_MERGE(v0, a0, p0, q0);
-                DRR_ACCUM(v1, a1, a0, p1, q1);
-                active = a0 < amax;
+    for (int it = 0; it < cap; ++it) {
+        if (active) {
+#pragma unroll
+            for (int k = 0; k < NR; ++k) {
+                const int m = (k + DEPTH) % NR;
+                DRR_MERGE(v[m], a[m], p[m], q[m]);
+                DRR_ACCUM(v[k], a[k], a[(k + 1) % NR], p[k], q[k]);
             }
-            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+            active = a[0] < amax_m;
         }
-    } else if (DEPTH == 2) {
-        // segment m = [a_m, a_{m+1}] with value v_m is closed while the merge
-        // produces crossing m + 2; names rotate with period three
-        float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f;
-        double a0 = amin, a1 = amin, a2 = amin;
-        float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f, p2 = 0.0f, q2 = 0.0f;
-        DRR_MERGE(v1, a1, p1, q1);
-        const int cap = (V.n[0] + V.n[1] + V.n[2] + 8) / 3;
-        for (int it = 0; it < cap; ++it) {
-            if (active) {
-                DRR_MERGE(v2, a2, p2, q2);
-                DRR_ACCUM(v0, a0, a1, p0, q0);
-                DRR_MERGE(v0, a0, p0, q0);
-                DRR_ACCUM(v1, a1, a2, p1, q1);
-                DRR_MERGE(v1, a1, p1, q1);
-                DRR_ACCUM(v2, a2, a0, p2, q2);
-                active = a0 < amax;
-            }
-            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
-        }
-    } else {
-        // depth 4: segment m is closed while the merge produces crossing
-        // m + 4; names rotate with period five
-        float v0 = ld(rsrc, off), v1 = 0.0f, v2 = 0.0f, v3 = 0.0f, v4 = 0.0f;
-        double a0 = amin, a1 = amin, a2 = amin, a3 = amin, a4 = amin;
-        float p0 = w1_entry, q0 = w2_entry, p1 = 0.0f, q1 = 0.0f, p2 = 0.0f, q2 = 0.0f,
-              p3 = 0.0f, q3 = 0.0f, p4 = 0.0f, q4 = 0.0f;
-        DRR_MERGE(v1, a1, p1, q1);
-        DRR_MERGE(v2, a2, p2, q2);
-        DRR_MERGE(v3, a3, p3, q3);
-        const int cap = (V.n[0] + V.n[1] + V.n[2] + 14) / 5;
-        for (int it = 0; it < cap; ++it) {
-            if (active) {
-                DRR_MERGE(v4, a4, p4, q4);
-                DRR_ACCUM(v0, a0, a1, p0, q0);
-                DRR_MERGE(v0, a0, p0, q0);
-                DRR_ACCUM(v1, a1, a2, p1, q1);
-                DRR_MERGE(v1, a1, p1, q1);
-                DRR_ACCUM(v2, a2, a3, p2, q2);
-                DRR_MERGE(v2, a2, p2, q2);
-                DRR_ACCUM(v3, a3, a4, p3, q3);
-                DRR_MERGE(v3, a3, p3, q3);
-                DRR_ACCUM(v4, a4, a0, p4, q4);
-                active = a0 < amax;
-            }
-            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
-        }
+        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
     }
 #undef DRR_MERGE
 #undef DRR_ACCUM
     r.sum = acc;
     r.nseg = nseg;
     if (JAC) {
+        // The pipeline's last DEPTH crossings (all at the clip, with jump 0)
+        // were merged but not accumulated: their R terms are added here, in
+        // merge order, so that the sums cover every crossing the merge took
+        // whatever the depth (an e1 or e2 plane that the repeated additions
+        // put exactly on the clip is taken there, once, and is the same
+        // crossing at every depth of at least 2).
+#pragma unroll
+        for (int k = 0; k < DEPTH; ++k) {
+            R1s = fmaf(__int_as_float(__double2hiint(p[k])), A1s, R1s);
+            R2s = fmaf(__int_as_float(__double2hiint(q[k])), A2s, R2s);
+        }
+        // crossings an axis advanced over: its alpha moved by whole steps
+        auto advances = [](double a_now, double a_first, double da) {
+            return (isfinite(a_first) && da > 0.0) ? rint((a_now - a_first) / da) : 0.0;
+        };
+        const double n1 = advances(a1, E1.a, d1 * 0x1p-7);
+        const double n2 = advances(a2, E2.a, d2 * 0x1p-7);
+        // (explicit fma: every instantiation rounds these the same way)
+        auto alpha_sum = [](double n, double a_first, double da, float A, float R) {
+            return n > 0.0 ? fma(a_first, (double)A, da * fma(n, (double)A, -(double)R)) : 0.0;
+        };
+        double B1 = alpha_sum(n1, E1.a, d1 * 0x1p-7, A1s, R1s);
+        double B2 = alpha_sum(n2, E2.a, d2 * 0x1p-7, A2s, R2s);
         // Ends clamped to alpha = 0 or 1 belong to no axis (sums Ac, Bc); the
         // derived axis takes what the identities leave:
         //   A_d = -(A_e1 + A_e2 + Ac),  B_d = E/|d| - B_e1 - B_e2 - Bc.
-        float Ac = 0.0f, Bc = 0.0f;
-        // entry clamped to alpha = 0 (source inside the grid): V_before = 0,
-        // V_after = the first voxel, alpha = 0
-        if (amin_ax < 0) Ac -= ld(rsrc, off_entry);
-        // exit crossing at amax: V_before = last voxel, V_after = 0
-        const float t = (float)amax;
+        float Ac = 0.0f;
+        double Bc = 0.0;
+        // entry crossing at alpha_min: V_before = 0, V_after = the first voxel
+        const float ventry = ld(rsrc, off_entry);
+        if (amin_ax == e1) {
+            A1s -= ventry;
+            B1 = fma(-amin, (double)ventry, B1);
+        } else if (amin_ax == e2) {
+            A2s -= ventry;
+            B2 = fma(-amin, (double)ventry, B2);
+        } else if (amin_ax < 0) {
+            Ac -= ventry;          // clamped to alpha = 0 (source inside the grid)
+        }
+        // exit crossing at alpha_max: V_before = last voxel, V_after = 0
         if (amax_ax == e1) {
             A1s += vprev;
-            B1s += t * vprev;
+            B1 = fma(amax, (double)vprev, B1);
         } else if (amax_ax == e2) {
             A2s += vprev;
-            B2s += t * vprev;
+            B2 = fma(amax, (double)vprev, B2);
         } else if (amax_ax < 0) {
             Ac += vprev;
-            Bc += t * vprev;
+            Bc = amax * (double)vprev;
         }
         const float Ad = -(A1s + A2s + Ac);
-        const float Bd = (float)(acc - (double)B1s - (double)B2s - (double)Bc);
+        const float Bd = (float)(acc - B1 - B2 - Bc);
         r.a0 = derived == 0 ? Ad : A1s;
-        r.b0 = derived == 0 ? Bd : B1s;
+        r.b0 = derived == 0 ? Bd : (float)B1;
         r.a1 = derived == 0 ? A1s : (derived == 1 ? Ad : A2s);
-        r.b1 = derived == 0 ? B1s : (derived == 1 ? Bd : B2s);
+        r.b1 = derived == 0 ? (float)B1 : (derived == 1 ? Bd : (float)B2);
         r.a2 = derived == 2 ? Ad : A2s;
-        r.b2 = derived == 2 ? Bd : B2s;
+        r.b2 = derived == 2 ? Bd : (float)B2;
     }
     return r;
 }

@@ -179,10 +179,12 @@ def test_deterministic_and_batch_independent(small):
 
 
 def test_pipeline_depth_does_not_change_results(small):
-    """Launches of up to 16 workgroups per CU run the depth-4 gather
-    pipeline, larger image launches depth 2: a pose renders bitwise the same
-    in a batch of 8 (depth 4) and in a batch of 300 (depth 2, 300 x 256
-    workgroups), and so do its gather counts."""
+    """Launches of at most one workgroup per CU run the depth-6 gather
+    pipeline, launches of up to 16 workgroups per CU depth 4, larger image
+    launches depth 2: a pose renders bitwise the same alone (depth 6), in a
+    batch of 8 (depth 4) and in a batch of 300 (depth 2, 300 x 256
+    workgroups), and so do its gather counts; the fused gradient of a pose
+    alone (depth 6) equals the same pose's in a batch of 8 (depth 4)."""
     P = _lib_objs()
     ph, vol, grid = small
     det = P.Detector(256, 256, 0.5, 0.5)          # 256 workgroups per pose
@@ -190,9 +192,18 @@ def test_pipeline_depth_does_not_change_results(small):
     big = P.render(vol, poses, det)
     few = P.render(vol, poses[:8].clone(), det)
     assert torch.equal(few, big[:8])
+    for k in (0, 5):
+        alone = P.render(vol, poses[k:k + 1].clone(), det)
+        assert torch.equal(alone[0], big[k])
     big_i, big_c = P.render_count(vol, poses, det)
     few_i, few_c = P.render_count(vol, poses[:8].clone(), det)
     assert torch.equal(few_c, big_c[:8]) and torch.equal(few_i, big_i[:8])
+    one_i, one_c = P.render_count(vol, poses[3:4].clone(), det)
+    assert torch.equal(one_c[0], big_c[3]) and torch.equal(one_i[0], big_i[3])
+    target = big[7]
+    l8, g8 = P.render_ncc_grad(vol, poses[:8].clone(), det, target)
+    l1, g1 = P.render_ncc_grad(vol, poses[2:3].clone(), det, target)
+    assert torch.equal(l1[0], l8[2]) and torch.equal(g1[0], g8[2])
 
 
 # ------------------------------------------------------------------ clinical size
