@@ -48,16 +48,24 @@ def parse():
     ap.add_argument("--only", choices=["fwd", "fwdbwd", "direct"], default=None,
                     help="time one phase only (for profiling runs)")
     ap.add_argument("--mode", choices=["drr", "register", "serve", "landscape", "table1",
-                                       "gather-calibration"],
+                                       "gather-calibration", "long-volume"],
                     default="drr",
                     help="drr: the headline forward / fwd+bwd batch (default); register: "
                          "32 batched registrations; serve: the request loop over four "
                          "resident volumes at a QPS sweep; landscape: loss sweeps over "
                          "random and gridded pose offsets; table1: the paper's PyTorch "
                          "formulations beside the kernel; gather-calibration: cost of one "
-                         "gather instruction against the cache lines it touches")
+                         "gather instruction against the cache lines it touches; long-volume: "
+                         "forward batches on the 512 x 512 x 300 CT, which does not fit the "
+                         "Infinity Cache")
     ap.add_argument("--requests", type=int, default=2000,
-                    help="requests per QPS point in --mode serve")
+                    help="requests per QPS point in --mode serve (and of the serving point of "
+                         "the default mode)")
+    ap.add_argument("--serve-qps", type=float, default=8000.0,
+                    help="offered rate of the serving point in the default mode")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="default mode: skip the serving point, the registration, the Table 1 "
+                         "row and the long-volume measurement")
     ap.add_argument("--tune-cache", default=os.path.join(
                         os.path.dirname(os.path.abspath(__file__)), "paper_2208_12737_amd",
                         "tuning.txt"),
@@ -178,22 +186,21 @@ def cpu_baseline(ph, poses, det_px, pitch, cpu_seconds):
             "cpu_model": model, "nproc": os.cpu_count()}
 
 
-def bench_register(args):
+def registration_run(vol, n=32, steps=200, chains_list=(1, 2, 4), reps=3,
+                     one_at_a_time=True):
     """32 registration problems on the 512 x 512 x 133 CT, 256 x 256
     detector: ground-truth poses (angles +-pi/6, shifts +-30 mm), starts
     offset by up to 15 deg / 25 mm per parameter, 200 steps of momentum
     gradient descent on -ZNCC with the step sizes of Sec. 3.2, all problems
-    in one captured graph; beside it the one-DRR-at-a-time autograd path."""
+    in one captured graph (problems split into independent chains); beside it
+    the one-DRR-at-a-time autograd path."""
     import torch
     import paper_2208_12737_amd as P
     from paper_2208_12737_amd.register import (BatchedRegistration, CONVERGED_LOSS,
                                                default_rates, pose_errors,
                                                register_one_at_a_time)
-    from synth import make_phantom, random_poses
+    from synth import random_poses
 
-    n, steps = 32, 200
-    ph = make_phantom("ct512", seed=0)
-    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
     det = P.Detector(256, 256, 1.4, 1.4)
     gt = random_poses(n, math.pi / 6, 30.0, 1020.0, seed=11)
     rng = np.random.default_rng(12)
@@ -203,16 +210,16 @@ def bench_register(args):
     targets = P.render(vol, torch.from_numpy(gt).cuda(), det)
     init = torch.from_numpy(gt + off).cuda()
     rates = default_rates(n)
-    # the problems advance as 1, 2 or 4 independent chains (graph branches);
-    # each problem's arithmetic is the same, so the results must be too
+    # each problem's arithmetic is the same in any grouping, so every chain
+    # count must give the same results
     sweep, runs = {}, {}
-    for chains in (1, 2, 4):
+    for chains in chains_list:
         reg = BatchedRegistration(vol, det, targets, init, rates, steps=steps, use_graph=True,
                                   chains=chains)
         reg.run()                                 # capture + first replay
         torch.cuda.synchronize()
         walls = []
-        for _ in range(max(args.steps // 8, 3)):
+        for _ in range(reps):
             a = torch.cuda.Event(enable_timing=True)
             b = torch.cuda.Event(enable_timing=True)
             a.record()
@@ -223,26 +230,19 @@ def bench_register(args):
         sweep[chains] = float(np.median(walls))
         runs[chains] = (poses.clone(), hist.clone())
         del reg
-    for chains in (2, 4):
-        if not (torch.equal(runs[chains][0], runs[1][0]) and
-                torch.equal(runs[chains][1], runs[1][1])):
-            raise RuntimeError(f"registration with {chains} chains differs from one chain")
+    c0 = chains_list[0]
+    for chains in chains_list[1:]:
+        if not (torch.equal(runs[chains][0], runs[c0][0]) and
+                torch.equal(runs[chains][1], runs[c0][1])):
+            raise RuntimeError(f"registration with {chains} chains differs from {c0}")
     best = min(sweep, key=sweep.get)
     t_batch = sweep[best]
     poses, hist = runs[best]
     h = hist.cpu().numpy()
     r_err, t_err = pose_errors(poses.cpu().numpy(), gt)
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    po, fl = register_one_at_a_time(vol, det, targets, init, rates, steps=steps)
-    torch.cuda.synchronize()
-    t_one = time.perf_counter() - t0
-    r1, t1 = pose_errors(po.cpu().numpy(), gt)
-    fl = fl.cpu().numpy()
     r0, t0e = pose_errors(gt + off, gt)
-    res = {"metric": "batched registration: wall time and final pose error", "mode": "register",
-           "problems": n, "steps": steps, "detector": [256, 256],
-           "volume": [512, 512, 133], "rates": {"rot": float(rates[0, 0]), "xyz": float(rates[0, 3])},
+    res = {"problems": n, "steps": steps, "detector": [256, 256], "volume": [512, 512, 133],
+           "rates": {"rot": float(rates[0, 0]), "xyz": float(rates[0, 3])},
            "initial_error_mean": {"rot_deg": float(r0.mean()), "trans_mm": float(t0e.mean())},
            "chains_wall_s": {str(c): w for c, w in sweep.items()},
            "batched_graph": {"chains": best, "wall_s": t_batch,
@@ -253,43 +253,57 @@ def bench_register(args):
                              "rot_err_deg_median": float(np.median(r_err)),
                              "trans_err_mm_median": float(np.median(t_err)),
                              "rot_err_deg_mean": float(r_err.mean()),
-                             "trans_err_mm_mean": float(t_err.mean())},
-           "one_at_a_time": {"wall_s": t_one, "converged": int((fl < CONVERGED_LOSS).sum()),
-                             "rot_err_deg_median": float(np.median(r1)),
-                             "trans_err_mm_median": float(np.median(t1))},
-           "speedup": t_one / t_batch, "data": "synthetic"}
+                             "trans_err_mm_mean": float(t_err.mean())}}
+    if one_at_a_time:
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        po, fl = register_one_at_a_time(vol, det, targets, init, rates, steps=steps)
+        torch.cuda.synchronize()
+        t_one = time.perf_counter() - t0
+        r1, t1 = pose_errors(po.cpu().numpy(), gt)
+        fl = fl.cpu().numpy()
+        res["one_at_a_time"] = {"wall_s": t_one, "converged": int((fl < CONVERGED_LOSS).sum()),
+                                "rot_err_deg_median": float(np.median(r1)),
+                                "trans_err_mm_median": float(np.median(t1))}
+        res["speedup"] = t_one / t_batch
+    return res
+
+
+def bench_register(args):
+    import torch
+    import paper_2208_12737_amd as P
+    from synth import make_phantom
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
+    res = {"metric": "batched registration: wall time and final pose error", "mode": "register"}
+    res.update(registration_run(vol, reps=max(args.steps // 8, 3)))
+    res["data"] = "synthetic"
     print(json.dumps(res), flush=True)
 
 
-def bench_serve(args):
-    """The request loop over four resident volumes (128^3 at 2 mm, 256^3 at
-    1 mm, 512 x 512 x 133, 512 x 512 x 300 at 0.7 x 0.7 x 1.25 mm): requests
-    with a random volume, a detector of 128^2 / 200^2 / 256^2 / 512^2 pixels
-    (pitch 358.4 mm / N, SDD 1020 mm), a random pose and a 70/30 split of
-    forward vs forward + backward (NCC gradient against a target rendered
-    near the pose), Poisson arrivals at a sweep of offered rates."""
+SERVE_VOLUMES = ["ct128", "ct256", "ct512", "ct512x300"]
+SERVE_DETECTORS = [128, 200, 256, 512]
+
+
+def serving_setup(vols):
+    """Request factory of the serving workload over the resident volumes
+    `vols` (names of SERVE_VOLUMES): a random volume, a detector of 128^2 /
+    200^2 / 256^2 / 512^2 pixels (pitch 358.4 mm / N, SDD 1020 mm), a random
+    pose and a 70/30 split of forward vs forward + backward (NCC gradient
+    against a target rendered near the pose)."""
     import torch
     import paper_2208_12737_amd as P
-    from paper_2208_12737_amd.serve import (FWD, FWDBWD, GpuBackend, Request, Server,
-                                            plain_forward)
-    from synth import make_phantom, random_poses
-
-    dev = "cuda"
-    names = ["ct128", "ct256", "ct512", "ct512x300"]
-    vols = {}
-    for nm in names:
-        print(f"[bench] phantom {nm}", file=sys.stderr, flush=True)
-        ph = make_phantom(nm, seed=0)
-        vols[nm] = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device=dev)
-    sizes = [128, 200, 256, 512]
-    rng = np.random.default_rng(7)
+    from paper_2208_12737_amd.serve import FWD, FWDBWD, Request
+    from synth import random_poses
+    names, sizes = SERVE_VOLUMES, SERVE_DETECTORS
     # a pool of targets per (volume, detector) for the forward + backward requests
     pool = {}
     for nm in names:
         for N in sizes:
-            gt = random_poses(4, math.pi / 6, 30.0, 1020.0, seed=10 * names.index(nm) + sizes.index(N))
+            gt = random_poses(4, math.pi / 6, 30.0, 1020.0,
+                              seed=10 * names.index(nm) + sizes.index(N))
             det = P.Detector(N, N, 358.4 / N, 358.4 / N)
-            pool[(nm, N)] = (gt, P.render(vols[nm], torch.from_numpy(gt).to(dev), det))
+            pool[(nm, N)] = (gt, P.render(vols[nm], torch.from_numpy(gt).cuda(), det))
 
     def make_requests(count, seed):
         r = np.random.default_rng(seed)
@@ -308,66 +322,100 @@ def bench_serve(args):
                 pose[3:6] += r.uniform(-1, 1, 3).astype(np.float32) * 5.0
                 out.append(Request(nm, N, N, 358.4 / N, 358.4 / N, pose, FWDBWD, tg[k]))
         return out
+    return make_requests
 
-    budget = 2 << 30
-    # one backend (streams, plan, warm allocator pools) serves every point
-    be = GpuBackend(vols, n_streams=3)
 
-    def run_point(reqs, qps):
-        import gc
-        srv = Server(be, hbm_budget_bytes=budget, n_streams=3, max_batch=256)
-        if qps is None:
-            arrivals = np.zeros(len(reqs))
-        else:
-            arrivals = np.cumsum(rng.exponential(1.0 / qps, len(reqs)))
-        torch.cuda.synchronize()
-        gc.collect()
-        gc.disable()                     # no collector pauses inside the timed loop
-        t0 = time.perf_counter()
-        tickets, k = [], 0
-        while k < len(reqs) or srv.pending():
-            now = time.perf_counter() - t0
-            while k < len(reqs) and arrivals[k] <= now:
-                reqs[k].arrival = t0 + arrivals[k]
-                tickets.append(srv.submit(reqs[k]))
-                k += 1
-            srv.tick()
-        torch.cuda.synchronize()
-        wall = time.perf_counter() - t0
-        gc.enable()
-        lat = np.array([t.latency for t in tickets]) * 1e3
-        return {"offered_qps": qps, "achieved_rps": len(reqs) / wall,
-                "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
-                "batches": srv.batches}
+def serving_point(be, reqs, qps, budget, rng):
+    """Serves `reqs` with Poisson arrivals at `qps` (None: all at once);
+    request latency is submission (arrival) to completion."""
+    import gc
+    import torch
+    from paper_2208_12737_amd.serve import Server
+    srv = Server(be, hbm_budget_bytes=budget, n_streams=3, max_batch=256)
+    if qps is None:
+        arrivals = np.zeros(len(reqs))
+    else:
+        arrivals = np.cumsum(rng.exponential(1.0 / qps, len(reqs)))
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()                     # no collector pauses inside the timed loop
+    t0 = time.perf_counter()
+    tickets, k = [], 0
+    while k < len(reqs) or srv.pending():
+        now = time.perf_counter() - t0
+        while k < len(reqs) and arrivals[k] <= now:
+            reqs[k].arrival = t0 + arrivals[k]
+            tickets.append(srv.submit(reqs[k]))
+            k += 1
+        srv.tick()
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    gc.enable()
+    lat = np.array([t.latency for t in tickets]) * 1e3
+    return {"offered_qps": qps, "achieved_rps": len(reqs) / wall, "requests": len(reqs),
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "batches": srv.batches}
 
-    print("[bench] serving: saturation", file=sys.stderr, flush=True)
-    warm = make_requests(200, seed=1)
-    run_point(warm, None)
-    sat = run_point(make_requests(args.requests, seed=2), None)
-    points = []
-    for frac in (0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2):
-        q = frac * sat["achieved_rps"]
-        print(f"[bench] serving at {q:.0f} req/s", file=sys.stderr, flush=True)
-        pt = run_point(make_requests(args.requests, seed=int(100 * frac) + 3), q)
-        pt["offered_frac_of_saturation"] = frac
-        points.append(pt)
-    # plain single-DRR forward path, one request at a time
-    reqs = [r for r in make_requests(400, seed=9) if r.kind == FWD]
+
+def plain_single_drr_path(vols, reqs):
+    """The plain single-DRR forward path, one request at a time: latency of
+    each (launch to completion)."""
+    import torch
+    from paper_2208_12737_amd.serve import FWD, plain_forward
     lat = []
     for r in reqs:
+        if r.kind != FWD:
+            continue
         torch.cuda.synchronize()
         t = time.perf_counter()
         plain_forward(vols, r)
         torch.cuda.synchronize()
         lat.append((time.perf_counter() - t) * 1e3)
     lat = np.array(lat)
+    return {"rps": float(1e3 / lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
+            "p99_ms": float(np.percentile(lat, 99)), "requests": len(lat)}
+
+
+def serving_volumes():
+    import torch
+    import paper_2208_12737_amd as P
+    from synth import make_phantom
+    vols, phs = {}, {}
+    for nm in SERVE_VOLUMES:
+        print(f"[bench] phantom {nm}", file=sys.stderr, flush=True)
+        ph = make_phantom(nm, seed=0)
+        vols[nm] = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
+        phs[nm] = ph
+    return vols, phs
+
+
+def bench_serve(args):
+    """The request loop over four resident volumes (128^3 at 2 mm, 256^3 at
+    1 mm, 512 x 512 x 133, 512 x 512 x 300 at 0.7 x 0.7 x 1.25 mm) with the
+    mixed detectors and 70/30 fwd / fwd+bwd split of serving_setup, Poisson
+    arrivals at a sweep of offered rates."""
+    from paper_2208_12737_amd.serve import GpuBackend
+    vols, _ = serving_volumes()
+    make_requests = serving_setup(vols)
+    rng = np.random.default_rng(7)
+    budget = 2 << 30
+    # one backend (streams, plan, warm allocator pools) serves every point
+    be = GpuBackend(vols, n_streams=3)
+    print("[bench] serving: saturation", file=sys.stderr, flush=True)
+    serving_point(be, make_requests(200, seed=1), None, budget, rng)
+    sat = serving_point(be, make_requests(args.requests, seed=2), None, budget, rng)
+    points = []
+    for frac in (0.1, 0.25, 0.4, 0.55, 0.7, 0.85, 1.0, 1.2):
+        q = frac * sat["achieved_rps"]
+        print(f"[bench] serving at {q:.0f} req/s", file=sys.stderr, flush=True)
+        pt = serving_point(be, make_requests(args.requests, seed=int(100 * frac) + 3), q,
+                           budget, rng)
+        pt["offered_frac_of_saturation"] = frac
+        points.append(pt)
     res = {"metric": "served requests/s and p50/p99 latency (ms), mixed volumes and detectors",
-           "mode": "serve", "volumes": names, "detectors": sizes, "fwd_fraction": 0.7,
-           "hbm_budget_bytes": budget, "saturation": sat, "sweep": points,
-           "plain_single_drr_forward": {"rps": float(1e3 / lat.mean()),
-                                        "p50_ms": float(np.percentile(lat, 50)),
-                                        "p99_ms": float(np.percentile(lat, 99)),
-                                        "requests": len(lat)},
+           "mode": "serve", "volumes": SERVE_VOLUMES, "detectors": SERVE_DETECTORS,
+           "fwd_fraction": 0.7, "hbm_budget_bytes": budget, "saturation": sat, "sweep": points,
+           "plain_single_drr_forward": plain_single_drr_path(vols, make_requests(400, seed=9)),
            "data": "synthetic"}
     print(json.dumps(res), flush=True)
 
@@ -528,17 +576,15 @@ def vgsj_torch(vol, spacing, origin, s, P):
     return torch.linalg.norm(d, dim=1) * acc
 
 
-def bench_table1(args):
+def table1_rows(vol, ph, sizes=(100, 200, 300, 400, 500)):
     """Table 1's comparison on one MI355X: the paper's two vectorised PyTorch
-    formulations against the hand-written kernel, for square detectors of
-    100 ... 500 pixels on the 512 x 512 x 133 CT (pitch 358.4 mm / N)."""
+    formulations against the hand-written kernel, for square detectors on
+    the 512 x 512 x 133 CT (pitch 358.4 mm / N), ms per DRR."""
     import torch
     import paper_2208_12737_amd as P
-    from synth import make_phantom, random_poses
+    from synth import random_poses
     dev = "cuda"
-    ph = make_phantom("ct512", seed=0)
     vol_t = torch.from_numpy(ph.volume).to(dev)
-    vol = P.Volume(vol_t, ph.spacing, ph.origin, device=dev)
     pose = random_poses(1, math.pi / 6, 30.0, 1020.0, seed=5)[0]
     rows = []
 
@@ -551,7 +597,7 @@ def bench_table1(args):
         torch.cuda.synchronize()
         return (time.perf_counter() - t0) / reps * 1e3
 
-    for N in (100, 200, 300, 400, 500):
+    for N in sizes:
         pitch = 358.4 / N
         det = P.Detector(N, N, pitch, pitch)
         s, Pp = _rays_torch(pose, N, N, pitch, dev)
@@ -570,9 +616,20 @@ def bench_table1(args):
         row["vgsj_ms"] = t_ms(lambda: vgsj_torch(vol_t, ph.spacing, ph.origin, s, Pp), 1)
         rows.append(row)
         print(f"[bench] table1 {row}", file=sys.stderr, flush=True)
+    del vol_t
+    return rows
+
+
+def bench_table1(args):
+    import torch
+    import paper_2208_12737_amd as P
+    from synth import make_phantom
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
     print(json.dumps({"metric": "ms per DRR: paper's VGS / VGSJ formulations (PyTorch) vs the "
-                      "hand-written kernel, one MI355X", "mode": "table1", "rows": rows,
-                      "volume": [512, 512, 133], "data": "synthetic"}), flush=True)
+                      "hand-written kernel, one MI355X", "mode": "table1",
+                      "rows": table1_rows(vol, ph), "volume": [512, 512, 133],
+                      "data": "synthetic"}), flush=True)
 
 
 def bench_gather_calibration(args):
@@ -608,6 +665,82 @@ def bench_gather_calibration(args):
                       "instr_per_wave": iters, "rows": rows}), flush=True)
 
 
+def long_volume_roofline(vol, det_sizes=(256, 512), rays=1 << 24, reps=10):
+    """Forward throughput on the 512 x 512 x 300 CT at 0.7 x 0.7 x 1.25 mm,
+    whose 315 MB copy does not fit the 256 MB Infinity Cache: direct
+    launches of 2^24 rays (256 poses of 256 x 256, 64 of 512 x 512), gathers
+    counted by the renderer's counting mode."""
+    import torch
+    import paper_2208_12737_amd as P
+    from paper_2208_12737_amd import _lib as L
+    from synth import random_poses
+    out = {}
+    for N in det_sizes:
+        det = P.Detector(N, N, 358.4 / N, 358.4 / N)
+        nb = max(1, rays // (N * N))
+        poses = torch.from_numpy(random_poses(nb, math.pi / 6, 30.0, 1020.0, seed=17)).cuda()
+        _, cnt = P.render_count(vol, poses, det)
+        gathers = int(cnt.to(torch.int64).sum().item())
+        img = torch.empty((nb, N, N), device="cuda")
+        f = lambda: L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc),
+                           ctypes.byref(det.desc), poses.data_ptr(), nb, img.data_ptr(), None,
+                           torch.cuda.current_stream().cuda_stream)
+        for _ in range(2):
+            f()
+        torch.cuda.synchronize()
+        ts = []
+        for _ in range(reps):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            f()
+            b.record()
+            torch.cuda.synchronize()
+            ts.append(a.elapsed_time(b))
+        t = float(np.median(ts)) / 1e3
+        nbytes = 4 * gathers + 4 * nb * N * N
+        out[f"det{N}"] = {"poses": nb, "ms_per_batch": t * 1e3, "drrs_per_s": nb / t,
+                          "gathers_per_ray": gathers / (nb * N * N),
+                          "gvox_gathers_per_s": gathers / t / 1e9,
+                          "algorithmic_GBps": nbytes / t / 1e9,
+                          "hbm_frac": nbytes / t / 8.0e12, "bytes_per_launch": nbytes}
+    return {"volume": [512, 512, 300], "spacing_mm": [0.7, 0.7, 1.25],
+            "copy_MB": vol.nbytes / 3 / 1e6, **out}
+
+
+def default_extras(args, vol, ph):
+    """The other workloads, compact, in the default run: one serving point of
+    the request loop beside the plain single-DRR path, the 32-problem batched
+    registration beside one-at-a-time, a Table 1 row and the volume that does
+    not fit the Infinity Cache."""
+    import torch
+    from paper_2208_12737_amd.serve import GpuBackend
+    out = {}
+    print("[bench] registration (32 problems x 200 steps)", file=sys.stderr, flush=True)
+    out["registration_32x200"] = registration_run(vol, chains_list=(2,), reps=3)
+    print("[bench] Table 1 row (200 x 200)", file=sys.stderr, flush=True)
+    out["table1_200x200"] = table1_rows(vol, ph, sizes=(200,))[0]
+    vols, _ = serving_volumes()
+    make_requests = serving_setup(vols)
+    be = GpuBackend(vols, n_streams=3)
+    rng = np.random.default_rng(7)
+    budget = 2 << 30
+    print(f"[bench] serving point at {args.serve_qps:.0f} req/s", file=sys.stderr, flush=True)
+    serving_point(be, make_requests(200, seed=1), None, budget, rng)      # warm-up
+    pt = serving_point(be, make_requests(args.requests, seed=3), args.serve_qps, budget, rng)
+    out["serving"] = {"volumes": SERVE_VOLUMES, "detectors": SERVE_DETECTORS,
+                      "fwd_fraction": 0.7, "hbm_budget_bytes": budget, "point": pt,
+                      "plain_single_drr_forward": plain_single_drr_path(
+                          vols, make_requests(400, seed=9)),
+                      "latency_is": "request arrival to completion, ms"}
+    del be
+    print("[bench] 512 x 512 x 300 volume", file=sys.stderr, flush=True)
+    out["long_volume_fwd"] = long_volume_roofline(vols["ct512x300"])
+    del vols
+    torch.cuda.empty_cache()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -632,6 +765,18 @@ def main():
         return
     if args.mode == "gather-calibration":
         bench_gather_calibration(args)
+        return
+    if args.mode == "long-volume":
+        import torch
+        import paper_2208_12737_amd as P
+        from synth import make_phantom
+        ph = make_phantom("ct512x300", seed=0)
+        vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
+        res = {"metric": "forward DRRs/s and algorithmic GB/s on a CT larger than the Infinity "
+                         "Cache", "mode": "long-volume"}
+        res.update(long_volume_roofline(vol, reps=max(args.steps // 20, 2)))
+        res["data"] = "synthetic"
+        print(json.dumps(res), flush=True)
         return
 
     import torch
@@ -805,9 +950,14 @@ def main():
               "fused_render_ncc_grad_ms": fused, "fused_drrs_per_s": 64e3 / fused,
               "autograd_stored_jacobian_ms": stored, "autograd_retrace_ms": retr}
 
+    extras = {} if args.no_extras or args.only else default_extras(args, vol, ph)
+
     res = {"metric": METRIC, "unit": "DRRs/s", "n_gpus": 1, "steps": args.steps,
            "warmup": args.warmup, "ms_per_step": float(step_ms.mean()),
-           "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+           "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+           "dtype": "f64 geometry / f32 data",
+           "dtype_detail": "FP64: crossing parameters, ray geometry, path sums, NCC moments; "
+                           "FP32: voxels, images, targets, per-ray Jacobian sums, poses",
            "data": "synthetic (seeded ellipsoid phantom, random poses)",
            "config": {"workload": "ct512x512x133_det256_poses256", "volume": [512, 512, 133],
                       "spacing_mm": [0.7, 0.7, 2.5], "detector": [H, W], "pitch_mm": pitch,
@@ -835,7 +985,16 @@ def main():
                                                     if "gather_floor_us" in prof else None),
                            "kernel": f"{plan_cfg['strategy']} plan kernel, image mode, tile "
                                      f"code {plan_cfg['tile_code']}, {plan_cfg['wg_per_cu']} WG/CU",
-                           "bytes_per_launch": bytes_fwd}
+                           "bytes_per_launch": bytes_fwd,
+                           "achieved_is": "algorithmic bytes (4 B per voxel gather + 4 B per "
+                                          "pixel) / event-timed launch",
+                           "measured_hbm_GBps": (prof["traffic_bytes_per_launch"] / t_fwd / 1e9
+                                                 if prof.get("traffic_bytes_per_launch") else None),
+                           "measured_hbm_frac": (prof["traffic_bytes_per_launch"] / t_fwd / 8.0e12
+                                                 if prof.get("traffic_bytes_per_launch") else None),
+                           "limiter": "L1 gather issue (texture addresser) and VALU issue; the "
+                                      "volume copy in use stays in the Infinity Cache, so HBM "
+                                      "traffic is below the algorithmic bytes"}
         res["plan"] = plan_cfg
     if "direct" in times:
         t_d = times["direct"].mean() / 1e3
@@ -856,12 +1015,18 @@ def main():
                                   "bytes_per_launch": fb_bytes}
         if "value" not in res:
             res["value"] = nb / t_fb
-    res["p50_ms"] = float(np.percentile(step_ms, 50))
-    res["p99_ms"] = float(np.percentile(step_ms, 99))
+    res["step_p50_ms"] = float(np.percentile(step_ms, 50))
+    res["step_p99_ms"] = float(np.percentile(step_ms, 99))
     if len(lat):
         res["single_drr_latency_ms"] = {"p50": float(np.percentile(lat, 50)),
                                         "p99": float(np.percentile(lat, 99)),
-                                        "drrs_per_s": float(1e3 / lat.mean())}
+                                        "drrs_per_s": float(1e3 / lat.mean()),
+                                        "note": "one 256 x 256 DRR per drr_render call, host "
+                                                "time from launch to completion"}
+        # the latency a request of the plain forward path sees
+        res["p50_ms"] = float(np.percentile(lat, 50))
+        res["p99_ms"] = float(np.percentile(lat, 99))
+        res["p99_is"] = "single-DRR latency (launch to completion), ms"
     if len(cold):
         res["single_drr_cold_cache_ms"] = {"p50": float(np.percentile(cold, 50)),
                                            "max": float(cold.max()),
@@ -869,6 +1034,7 @@ def main():
                                                    "write that evicts L2 and Infinity Cache"}
     if c3 is not None:
         res["differentiable_render_64x200x200"] = c3
+    res.update(extras)
     res["wall_s_timed"] = wall
     if not args.no_cpu_baseline:
         print("[bench] timing the CPU oracle", file=sys.stderr, flush=True)

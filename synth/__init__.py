@@ -9,14 +9,10 @@ of the computation under test.
 
 from .phantom import Phantom, make_phantom, ellipsoid_phantom
 from .poses import random_poses
-from .workloads import WORKLOADS, Workload, workload
 
 __all__ = [
     "Phantom",
     "make_phantom",
     "ellipsoid_phantom",
     "random_poses",
-    "WORKLOADS",
-    "Workload",
-    "workload",
 ]
