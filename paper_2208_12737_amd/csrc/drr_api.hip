@@ -86,6 +86,23 @@ static int32_t launch_flat(const void* packed, const drr_volume_desc& vol,
     // of at most one workgroup per CU (a single DRR of up to 256 x 256
     // pixels) leave each SIMD one wave and take the deepest pipeline
     const uint64_t cus = (uint64_t)num_cus();
+    if constexpr (MODE == kImage || MODE == kCount) {
+        // per-pixel results that do not depend on the launch shape: a launch
+        // of at most one workgroup per CU uses 8 x 8-pixel waves (16 x 16
+        // pixels per workgroup), whose rays gather from fewer cache lines per
+        // step than 4 x 16-pixel waves; it left a lone wave per SIMD either way
+        using TS = TileShape<8, 2, 2>;
+        const int tx = (det.width + TS::px_w - 1) / TS::px_w;
+        const uint64_t tb = (uint64_t)tx * (uint64_t)((det.height + TS::px_h - 1) / TS::px_h) *
+                            (uint64_t)n_poses;
+        if (tb <= cus) {
+            hipLaunchKernelGGL((render_flat<8, 2, 2, MODE, kTinyDepth>), dim3((unsigned)tb),
+                               dim3(TS::threads), 0, stream, vol_args(packed, vol), det_args(det),
+                               poses, tx, (int)(tb / (uint64_t)n_poses), image, jac, counts, aux,
+                               aux_stride, partials);
+            return check_launch("render kernel launch");
+        }
+    }
     auto kernel = blocks <= cus ? render_flat<kTW, kWX, kWY, MODE, kTinyDepth>
                   : blocks <= 16ull * cus ? render_flat<kTW, kWX, kWY, MODE, kDeepDepth>
                                           : render_flat<kTW, kWX, kWY, MODE, full_depth<MODE>()>;
