@@ -153,8 +153,11 @@ __global__ __launch_bounds__(64 * WX * WY) void render_persistent(const char* __
         o.counts = it.counts;
         o.aux = MODE == kNcc ? it.target : nullptr;
         o.partial = MODE == kNcc ? it.partials + (int64_t)local * kNccSums : nullptr;
-        render_tile<TW, WX, WY, MODE, full_depth<MODE>()>(it.vol, it.det, it.pose, tx, ty, o,
-                                                           lds);
+        // (lean in the Jacobian modes: the loop over tiles and the item
+        // fields would otherwise push them past 128 VGPRs, below four waves
+        // per SIMD)
+        render_tile<TW, WX, WY, MODE, full_depth<MODE>(), ModeTraits<MODE>::jac>(
+            it.vol, it.det, it.pose, tx, ty, o, lds);
     }
     (void)sizeof(S);
 }

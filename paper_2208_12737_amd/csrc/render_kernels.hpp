@@ -98,7 +98,12 @@ __device__ inline void block_sums(double (&vals)[NS], double* lds, double* out)
 // Always inlined: an out-of-line call (the plan kernels have two call sites
 // per instance) passes the volume and detector fields in vector registers and
 // turns their uses into per-lane loads.
-template <int TW, int WX, int WY, int MODE, int DEPTH>
+// LEAN: for kernels that carry more state of their own (the persistent plan
+// kernels, short of scalar registers), the pose's trigonometry is evaluated
+// per lane and rebuilt in the Jacobian tail rather than kept through the
+// loop, and the Jacobian loop is the masked one only (see trace()); the
+// results are the same bits.
+template <int TW, int WX, int WY, int MODE, int DEPTH, bool LEAN = false>
 __device__ __forceinline__ void render_tile(const VolArgs& V, const DetArgs& D,
                                             const float* __restrict__ pose, int tx, int ty,
                                             const TileOut& o, double* lds)
@@ -111,7 +116,7 @@ __device__ __forceinline__ void render_tile(const VolArgs& V, const DetArgs& D,
     const int h = (ty * WY + wy) * S::th + lane / TW;
     const bool inside = (w < D.W) && (h < D.H);
 
-    const PoseTrig q = pose_trig(pose);
+    const PoseTrig q = LEAN ? pose_trig_per_lane(pose) : pose_trig(pose);
     const Mat3 R = rotation(q.ct, q.st, q.cp, q.sp, q.cg, q.sg, -1);
     const double u = ((double)w + 0.5 - 0.5 * (double)D.W) * (double)D.dx + D.ou;
     const double v = ((double)h + 0.5 - 0.5 * (double)D.H) * (double)D.dy + D.ov;
@@ -152,11 +157,11 @@ __device__ __forceinline__ void render_tile(const VolArgs& V, const DetArgs& D,
         if (!T::jac)
             r = trace<false, T::count, 0, DEPTH>(V, rsrc, pitch, s, d);
         else if (derived == 0)
-            r = trace<T::jac, T::count, 0, DEPTH>(V, rsrc, pitch, s, d);
+            r = trace<T::jac, T::count, 0, DEPTH, !LEAN>(V, rsrc, pitch, s, d);
         else if (derived == 1)
-            r = trace<T::jac, T::count, 1, DEPTH>(V, rsrc, pitch, s, d);
+            r = trace<T::jac, T::count, 1, DEPTH, !LEAN>(V, rsrc, pitch, s, d);
         else
-            r = trace<T::jac, T::count, 2, DEPTH>(V, rsrc, pitch, s, d);
+            r = trace<T::jac, T::count, 2, DEPTH, !LEAN>(V, rsrc, pitch, s, d);
     }
 
     const double L = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
@@ -165,11 +170,9 @@ __device__ __forceinline__ void render_tile(const VolArgs& V, const DetArgs& D,
 
     float J[7], Jp[4];
     if (T::jac) {
+        const PoseTrig qt = LEAN ? pose_trig_per_lane(launder(pose)) : q;
         if (inside && r.valid) {
-            // the pose frame is rebuilt here rather than kept in registers
-            // through the traversal loop
-            const PoseTrig q2 = pose_trig(launder(pose));
-            ray_jacobian(r, q2, u, v, J, MODE == kJacDet ? Jp : nullptr,
+            ray_jacobian(r, qt, u, v, J, MODE == kJacDet ? Jp : nullptr,
                          (double)w + 0.5 - 0.5 * (double)D.W, (double)h + 0.5 - 0.5 * (double)D.H);
         } else {
 #pragma unroll
@@ -234,6 +237,26 @@ __device__ __forceinline__ void render_tile(const VolArgs& V, const DetArgs& D,
     }
 }
 
+// Pose and tile of workgroup `bid` of a flat launch.  Hardware dispatch
+// deals consecutive workgroup ids to the 8 XCDs in turn.  When a pose's tile
+// count divides by 8, the XCDs advance through the poses together, each
+// taking a contiguous band of every pose's tiles (neighbouring tiles share
+// its L2, and the poses being traced at once are few, which spares the
+// Infinity Cache); otherwise each XCD takes a contiguous range of the
+// launch's tiles.  Which workgroup traces a tile never changes a result.
+__device__ inline void pose_tile(uint32_t bid, uint32_t total, uint32_t tiles, int* b, int* t)
+{
+    if (tiles % 8u == 0u) {
+        const uint32_t k = bid % tiles;
+        *b = (int)(bid / tiles);
+        *t = (int)((k % 8u) * (tiles / 8u) + k / 8u);
+    } else {
+        const uint32_t logical = xcd_logical(bid, total);
+        *b = (int)(logical / tiles);
+        *t = (int)(logical % tiles);
+    }
+}
+
 // Flat launch: grid = wg_per_pose * n_poses workgroups, XCD-aware ordering.
 template <int TW, int WX, int WY, int MODE, int DEPTH>
 __global__ __launch_bounds__(64 * WX * WY) void render_flat(
@@ -244,9 +267,8 @@ __global__ __launch_bounds__(64 * WX * WY) void render_flat(
     using T = ModeTraits<MODE>;
     __shared__ double lds[(T::nsum > 0 ? T::nsum : 1) * WX * WY];
     static_assert(sizeof(lds) == tile_sum_lds_bytes(T::nsum, WX * WY), "static LDS budget");
-    const uint32_t logical = xcd_logical(blockIdx.x, gridDim.x);
-    const int b = (int)(logical / (uint32_t)wg_per_pose);
-    const int t = (int)(logical % (uint32_t)wg_per_pose);
+    int b, t;
+    pose_tile(blockIdx.x, gridDim.x, (uint32_t)wg_per_pose, &b, &t);
     const int ty = t / tiles_x, tx = t % tiles_x;
     const int64_t hw = (int64_t)D.H * D.W;
     TileOut o;

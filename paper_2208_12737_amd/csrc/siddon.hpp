@@ -98,7 +98,42 @@ struct PoseTrig {
     double t[3];
 };
 
+// Value of x in lane `lane` of the wave (a scalar, uniform result).
+__device__ inline double lane_value(double x, int lane)
+{
+    const int lo = __builtin_amdgcn_readlane(__double2loint(x), lane);
+    const int hi = __builtin_amdgcn_readlane(__double2hiint(x), lane);
+    return __hiloint2double(hi, lo);
+}
+
+// The pose's trigonometry, once per wave: lanes 0, 1 and 2 evaluate the sine
+// and cosine of the three angles in one vector sincos, and every lane reads
+// the results back as wave-uniform (scalar) values.  Every lane of the wave
+// must be active.
 __device__ inline PoseTrig pose_trig(const float* __restrict__ pose)
+{
+    const int lane = (int)(threadIdx.x & 63);
+    const float ang = lane == 0 ? pose[0] : (lane == 1 ? pose[1] : pose[2]);
+    double sn, cs;
+    sincos((double)ang, &sn, &cs);
+    PoseTrig q;
+    q.st = lane_value(sn, 0);
+    q.ct = lane_value(cs, 0);
+    q.sp = lane_value(sn, 1);
+    q.cp = lane_value(cs, 1);
+    q.sg = lane_value(sn, 2);
+    q.cg = lane_value(cs, 2);
+    q.t[0] = pose[3];
+    q.t[1] = pose[4];
+    q.t[2] = pose[5];
+    q.rho = 0.5 * (double)pose[6];
+    return q;
+}
+
+// The same, evaluated by every lane (vector registers).  Kernels short of
+// scalar registers use this form: there the wave-uniform values above would
+// be spilled to vector registers while the traversal runs.
+__device__ inline PoseTrig pose_trig_per_lane(const float* __restrict__ pose)
 {
     PoseTrig q;
     sincos((double)pose[0], &q.st, &q.ct);
@@ -163,7 +198,11 @@ __device__ inline double min_nn(double a, double b)
 // |d| / |d_DERIVED| stays small for every ray of the wave.  (A template
 // argument: with a run-time axis the compiler selects between the per-lane
 // crossing masks with several VALU instructions per step.)
-template <bool JAC, bool COUNT, int DERIVED, int DEPTH>
+// FOLDED_LOOP: compile the Jacobian loop without the exit mask for waves
+// whose rays all fold their exit (see `clip`); without it every wave takes
+// the masked loop, which gives the same bits at some 2 VALU instructions
+// more per step and a few registers fewer.
+template <bool JAC, bool COUNT, int DERIVED, int DEPTH, bool FOLDED_LOOP = true>
 __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& rsrc,
                                const int32_t pitch[3], const double s[3], const double d[3])
 {
@@ -187,6 +226,12 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // Entry and exit parameters (Sec. 2.3), clamped to [0, 1].
     double amin = 0.0, amax = 1.0;
     int amin_ax = -1, amax_ax = -1;
+    // Bound on how far the exit face's parameter, as the loop reaches it by
+    // repeated steps, can lie from amax: the plane positions and the
+    // divisions round within a few ulps of the largest coordinate involved
+    // (scaled by 1 / |d_c| into alpha), and each of at most n_c + 4 steps
+    // rounds by at most half an ulp of an alpha <= 1 (bounds doubled here).
+    double amax_err = 0.0;
     bool miss = false;
     double o[3], sp[3];
 #pragma unroll
@@ -205,6 +250,8 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
             if (hi < amax) {
                 amax = hi;
                 amax_ax = c;
+                const double P = fmax(fmax(fabs(o[c]), fabs(hi_plane)), fabs(s[c]));
+                amax_err = (8.0 * P / fabs(d[c]) + (double)(V.n[c] + 4)) * 0x1p-52;
             }
         } else if (!(s[c] >= o[c] && s[c] < hi_plane)) {
             miss = true;
@@ -275,22 +322,41 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // crossings, and the sum R of A after each of them (B = sum alpha *
     // jump follows from A and R, see below)
     float A1s = 0.f, A2s = 0.f, R1s = 0.f, R2s = 0.f;
-    // The traversal clips at the double just below alpha_max: a plane of e1
-    // or e2 that the repeated additions land exactly on alpha_max is then
-    // not taken at the exit (no merge step ever picks it), so the crossings
-    // those axes advance over are the same whatever the pipeline depth.
-    // The last segment is one ulp of alpha short (a relative change of
-    // about 1e-16 of the path sum).
+    // Where the traversal stops (`clip`: the merge never returns a crossing
+    // beyond it).
+    //  * Exit through a face of the grid, computed well enough (folded):
+    //    the clip lies a margin past alpha_max, below a quarter of every
+    //    axis's step and 2^-37 (so below the sliver threshold), and at least
+    //    four error bounds away.  The loop then takes the exit face's own
+    //    crossing into the zero border (its jump, last voxel minus 0, is the
+    //    exit term of the Jacobian sums) and at most one further crossing per
+    //    axis, all between border voxels (jump 0, value 0).  Crossings at or
+    //    beyond the clip are the derived axis's (weight 0) or, exactly at the
+    //    clip, between border voxels: nothing past the clip changes a sum,
+    //    so the loop needs no exit mask.
+    //  * Otherwise (an end clamped to alpha = 1, or an exit face too close
+    //    to parallel to the ray): the double just below alpha_max, as plain
+    //    Siddon.  A plane of e1 or e2 that the repeated additions land
+    //    exactly on alpha_max is then never taken; one landing on the clip
+    //    itself is taken with jump 0 (the masked accumulation below).  The
+    //    last segment is one ulp of alpha short (about 1e-16 of the sum).
+    // Either way the crossings and sums are the same at every pipeline depth.
     const double amax_m = __longlong_as_double(__double_as_longlong(amax) - 1);
+    auto step_or_inf = [](double da) { return da > 0.0 ? da : __builtin_inf(); };
+    const double margin =
+        fmin(0x1p-37, 0.25 * fmin(fmin(step_or_inf(X0.da), step_or_inf(Y0.da)), step_or_inf(Z0.da)));
+    const bool fold = amax_ax >= 0 && 4.0 * amax_err <= margin;
+    const double clip = fold ? amax + margin : amax_m;
 
     // The traversal is split into a merge (pick the next crossing, advance
     // that axis, issue the gather of the voxel beyond it) and an accumulation
     // (add a closed segment's length x value).  The merge runs DEPTH
     // crossings ahead of the accumulation, so every gather has DEPTH merge
     // steps of independent work between its issue and its use.  The
-    // in-flight values live in DEPTH + 1 registers whose roles rotate
-    // through a fully unrolled loop (constant indices only): a copy of a
-    // loaded value would force an early wait on the load.
+    // in-flight values live in DEPTH + 1 registers (DEPTH + 2 in the folded
+    // Jacobian loop) whose roles rotate through a fully unrolled loop
+    // (constant indices only): a copy of a loaded value would force an early
+    // wait on the load.
     // (Macros rather than lambdas: a by-reference closure makes the compiler
     // keep the strides on the stack and load them every step.)
     //
@@ -302,7 +368,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     // 0) and closes empty segments.
 #define DRR_MERGE(vn, a_new, f1_new, f2_new)                                     \
     do {                                                                         \
-        const double anext = min_nn(min_nn(a1, a2), min_nn(ad, amax_m));         \
+        const double anext = min_nn(min_nn(a1, a2), min_nn(ad, clip));           \
         const bool b1 = a1 == anext;                                             \
         const bool b2 = !b1 && a2 == anext;                                      \
         const bool bd = (!b1) != b2;      /* = !b1 && !b2, as b2 implies !b1 */ \
@@ -328,8 +394,9 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
     } while (0)
     // Closes segment [a_start, a_end] in the voxel of value vc; the crossing
     // at a_start (weights w1, w2) has V_before = vprev and V_after = vc.
-    // Crossings at or after the clip change nothing (their jump is 0, and
-    // they are the derived axis's, of weight 0).
+    // Crossings at or after the clip change nothing (DRR_ACCUM masks their
+    // jump to 0; they are the derived axis's, of weight 0, or lie exactly on
+    // the clip).
     // Crossing m of an axis lies at alpha = a_first + (m - 1) da, so with the
     // running sums A_m and R = sum_m A_m over its n crossings,
     //   sum_m alpha_m jump_m = a_first A_n + da (n A_n - R),
@@ -344,7 +411,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         if (JAC) {                                                               \
             const float w1 = __int_as_float(__double2hiint(f1));                 \
             const float w2 = __int_as_float(__double2hiint(f2));                 \
-            const float vnew = (a_start) < amax_m ? (vc) : vprev;                \
+            const float vnew = (a_start) < clip ? (vc) : vprev;                  \
             const float dl = vprev - vnew;                                       \
             A1s = fmaf(w1, dl, A1s);                                             \
             R1s = fmaf(w1, A1s, R1s);                                            \
@@ -354,60 +421,128 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         }                                                                        \
     } while (0)
 
-    // Every crossing either ends the ray or advances an axis by one plane,
-    // so n_x + n_y + n_z + 4 steps bound the loop for any input.  The loop
+    // The same without the mask, for waves whose rays all fold their exit
+    // into the loop: there the jumps at or after the clip are either of
+    // weight 0 or between border voxels, and vp is the previous segment's
+    // value, still in its in-flight register.
+#define DRR_ACCUM_FOLDED(vc, vp, a_start, a_end, f1, f2)                         \
+    do {                                                                         \
+        const double seg = (a_end) - (a_start);                                  \
+        acc = fma(seg, (double)(vc), acc);                                       \
+        const float w1 = __int_as_float(__double2hiint(f1));                     \
+        const float w2 = __int_as_float(__double2hiint(f2));                     \
+        const float dl = (vp) - (vc);                                            \
+        A1s = fmaf(w1, dl, A1s);                                                 \
+        R1s = fmaf(w1, A1s, R1s);                                                \
+        A2s = fmaf(w2, dl, A2s);                                                 \
+        R2s = fmaf(w2, A2s, R2s);                                                \
+    } while (0)
+
+    // Every crossing either ends the ray or advances an axis by one plane
+    // (with a folded exit, at most once more per axis past the exit face),
+    // so n_x + n_y + n_z + 8 steps bound the loop for any input.  The loop
     // is wave-uniform; lanes that finished idle under the exec mask.  All
     // steps of an iteration run for a live lane (steps after the exit close
     // empty segments), which keeps each load ahead of its use.
-    constexpr int NR = DEPTH + 1;   // in-flight registers
-    float v[NR];
-    double a[NR], p[NR], q[NR];     // p, q: step factors of axes e1, e2
-    // (the entry crossing at alpha_min is not one of an axis's loop
-    // crossings: it is added after the loop, and has weight 0 here)
-    v[0] = ld(rsrc, off);
-    a[0] = amin;
-#pragma unroll
-    for (int k = 0; k < NR; ++k) {
-        if (k > 0) {
-            v[k] = 0.0f;
-            a[k] = amin;
-        }
-        p[k] = q[k] = 0.0;
-    }
-#pragma unroll
-    for (int k = 1; k < DEPTH; ++k) DRR_MERGE(v[k], a[k], p[k], q[k]);
-    // iteration: segment k = [a_k, a_{k+1}] is closed while the merge
-    // produces the crossing DEPTH places ahead, into register (k + DEPTH) % NR
-    const int cap = (V.n[0] + V.n[1] + V.n[2] + 3 * DEPTH + 2) / NR;
-    bool active = true;
-    for (int it = 0; it < cap; ++it) {
-        if (active) {
+    // Iteration: segment k = [a_k, a_{k+1}] is closed while the merge
+    // produces the crossing DEPTH places ahead, into register (k + DEPTH) % NR.
+    // (The entry crossing at alpha_min is not one of an axis's loop
+    // crossings: it is added after the loop, and has weight 0 here.)
+    // After the loop, the pipeline's last DEPTH crossings (registers 0 ..
+    // DEPTH - 1, all at the clip, with jump 0) have been merged but not
+    // accumulated: their R terms are added in merge order, so that the sums
+    // cover every crossing the merge took whatever the depth.
+    const int n_all = V.n[0] + V.n[1] + V.n[2];
+    bool folded_loop = false;
+    if constexpr (JAC && FOLDED_LOOP) folded_loop = __builtin_amdgcn_ballot_w64(!fold) == 0;
+    if constexpr (JAC && FOLDED_LOOP) {
+        if (folded_loop) {
+            // one more in-flight register, so that the previous segment's
+            // value is still held when the next segment closes
+            constexpr int NR = DEPTH + 2;
+            float v[NR];
+            double a[NR], p[NR], q[NR];   // p, q: step factors of axes e1, e2
+            v[0] = ld(rsrc, off);
+            a[0] = amin;
 #pragma unroll
             for (int k = 0; k < NR; ++k) {
-                const int m = (k + DEPTH) % NR;
-                DRR_MERGE(v[m], a[m], p[m], q[m]);
-                DRR_ACCUM(v[k], a[k], a[(k + 1) % NR], p[k], q[k]);
+                if (k > 0) {
+                    v[k] = 0.0f;
+                    a[k] = amin;
+                }
+                p[k] = q[k] = 0.0;
             }
-            active = a[0] < amax_m;
+#pragma unroll
+            for (int k = 1; k < DEPTH; ++k) DRR_MERGE(v[k], a[k], p[k], q[k]);
+            const int cap = (n_all + 2 * NR + 8) / NR + 2;
+            bool active = true;
+            for (int it = 0; it < cap; ++it) {
+                if (active) {
+#pragma unroll
+                    for (int k = 0; k < NR; ++k) {
+                        const int m = (k + DEPTH) % NR;
+                        DRR_MERGE(v[m], a[m], p[m], q[m]);
+                        DRR_ACCUM_FOLDED(v[k], v[(k + NR - 1) % NR], a[k], a[(k + 1) % NR],
+                                         p[k], q[k]);
+                    }
+                    active = a[0] < clip;
+                }
+                if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+            }
+#pragma unroll
+            for (int k = 0; k < DEPTH; ++k) {
+                R1s = fmaf(__int_as_float(__double2hiint(p[k])), A1s, R1s);
+                R2s = fmaf(__int_as_float(__double2hiint(q[k])), A2s, R2s);
+            }
+            // the exit crossing was taken in the loop: the traversal ends in
+            // the border, as the masked loop's vprev does for a folded ray
+            vprev = 0.0f;
         }
-        if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+    }
+    if (!folded_loop) {
+        constexpr int NR = DEPTH + 1;
+        float v[NR];
+        double a[NR], p[NR], q[NR];
+        v[0] = ld(rsrc, off);
+        a[0] = amin;
+#pragma unroll
+        for (int k = 0; k < NR; ++k) {
+            if (k > 0) {
+                v[k] = 0.0f;
+                a[k] = amin;
+            }
+            p[k] = q[k] = 0.0;
+        }
+#pragma unroll
+        for (int k = 1; k < DEPTH; ++k) DRR_MERGE(v[k], a[k], p[k], q[k]);
+        const int cap = (n_all + 2 * NR + 8) / NR + 2;
+        bool active = true;
+        for (int it = 0; it < cap; ++it) {
+            if (active) {
+#pragma unroll
+                for (int k = 0; k < NR; ++k) {
+                    const int m = (k + DEPTH) % NR;
+                    DRR_MERGE(v[m], a[m], p[m], q[m]);
+                    DRR_ACCUM(v[k], a[k], a[(k + 1) % NR], p[k], q[k]);
+                }
+                active = a[0] < clip;
+            }
+            if (__builtin_amdgcn_ballot_w64(active) == 0) break;
+        }
+        if (JAC) {
+#pragma unroll
+            for (int k = 0; k < DEPTH; ++k) {
+                R1s = fmaf(__int_as_float(__double2hiint(p[k])), A1s, R1s);
+                R2s = fmaf(__int_as_float(__double2hiint(q[k])), A2s, R2s);
+            }
+        }
     }
 #undef DRR_MERGE
 #undef DRR_ACCUM
+#undef DRR_ACCUM_FOLDED
     r.sum = acc;
     r.nseg = nseg;
     if (JAC) {
-        // The pipeline's last DEPTH crossings (all at the clip, with jump 0)
-        // were merged but not accumulated: their R terms are added here, in
-        // merge order, so that the sums cover every crossing the merge took
-        // whatever the depth (an e1 or e2 plane that the repeated additions
-        // put exactly on the clip is taken there, once, and is the same
-        // crossing at every depth of at least 2).
-#pragma unroll
-        for (int k = 0; k < DEPTH; ++k) {
-            R1s = fmaf(__int_as_float(__double2hiint(p[k])), A1s, R1s);
-            R2s = fmaf(__int_as_float(__double2hiint(q[k])), A2s, R2s);
-        }
         // crossings an axis advanced over: its alpha moved by whole steps
         auto advances = [](double a_now, double a_first, double da) {
             return (isfinite(a_first) && da > 0.0) ? rint((a_now - a_first) / da) : 0.0;
@@ -436,7 +571,8 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
         } else if (amin_ax < 0) {
             Ac -= ventry;          // clamped to alpha = 0 (source inside the grid)
         }
-        // exit crossing at alpha_max: V_before = last voxel, V_after = 0
+        // exit crossing at alpha_max: V_before = last voxel, V_after = 0 (a
+        // folded exit was taken in the loop, and vprev is then the border's 0)
         if (amax_ax == e1) {
             A1s += vprev;
             B1 = fma(amax, (double)vprev, B1);

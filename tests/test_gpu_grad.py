@@ -94,6 +94,44 @@ def test_jacobian_rays_parallel_to_planes(small, axis):
     assert max(errs) <= JAC_RTOL, errs
 
 
+def test_folded_and_masked_exits_agree():
+    """The detector plane cuts the grid, so some rays end inside it (alpha =
+    1, traced by the masked loop) and the rest leave through a face (their
+    exit crossing folded into the loop, unless their wave also holds a ray
+    that ends inside).  The same rays on a detector three pixels larger on
+    every side (so each wave holds other neighbours, and face-exit rays next
+    to the boundary change loop) give bitwise the same image and Jacobian;
+    the image mode gives the same image; all against the oracle.  The grid is
+    non-zero up to its faces, so every exit term counts."""
+    import paper_2208_12737_amd as P
+    rng = np.random.default_rng(77)
+    dims, spacing = (40, 36, 44), (1.0, 1.2, 0.9)
+    ext = np.asarray(dims) * np.asarray(spacing)
+    origin = tuple(float(v) for v in -0.5 * ext)
+    data = rng.uniform(0.2, 2.0, dims).astype(np.float32)
+    vol = P.Volume(torch.from_numpy(data), spacing, origin, device=DEV)
+    grid = oracle.Grid(data, spacing, origin)
+    # source at x ~ +44 mm (outside), detector plane at x ~ -16 mm (inside)
+    pose = np.array([[0.05, -0.04, 0.03, 14.0, 0.5, -0.7, 60.0]], np.float32)
+    H = W = 30
+    small_det, big_det = P.Detector(H, W, 2.0, 2.0), P.Detector(H + 6, W + 6, 2.0, 2.0)
+    p64 = pose[0].astype(np.float64)
+    inside = np.array([[np.all((oracle.ray_endpoints(p64, H, W, 2.0, 2.0, h, w)[1] > origin)
+                               & (oracle.ray_endpoints(p64, H, W, 2.0, 2.0, h, w)[1]
+                                  < np.asarray(origin) + ext))
+                        for w in range(W)] for h in range(H)])
+    assert 100 < inside.sum() < H * W - 100, inside.sum()
+    ia, ja = P.render(vol, _gpu(pose), small_det, jacobian=True)
+    ib, jb = P.render(vol, _gpu(pose), big_det, jacobian=True)
+    assert torch.equal(ia[0], ib[0, 3:3 + H, 3:3 + W])
+    assert torch.equal(ja[0], jb[0, 3:3 + H, 3:3 + W])
+    assert torch.equal(P.render(vol, _gpu(pose), small_det), ia)
+    rimg, rjac = oracle.render_jacobian(grid, p64[None], H, W, 2.0, 2.0, nthreads=4)
+    assert_image_close(ia.cpu().numpy(), rimg)
+    errs = column_errors(ja.cpu().numpy()[0], rjac[0])
+    assert max(errs) <= JAC_RTOL, errs
+
+
 def test_jacobian_with_clamped_ends(small):
     """Source and detector inside the volume (SDD 40 mm in a 64 mm cube): the
     ray ends are clamped to alpha = 0 and 1 and belong to no plane.  GPU
