@@ -7,13 +7,14 @@ and batched registration.  Importing the package does not load the library;
 the first call does, and raises if it is missing.
 """
 
-from .drr import (Detector, Volume, drr, momentum_step, ncc_loss, render, render_backward,
+from .drr import (Detector, Volume, choose_layout, drr, momentum_step, ncc_loss, render, render_backward,
                   render_backward_retrace, render_count, render_l2, render_ncc_grad,
                   render_ncc_loss, render_detector_jacobian)
 
 __all__ = [
     "Detector",
     "Volume",
+    "choose_layout",
     "drr",
     "momentum_step",
     "ncc_loss",

@@ -208,6 +208,7 @@ __device__ inline RayAcc trace(const VolArgs& V, const __amdgpu_buffer_rsrc_t& r
 {
     static_assert(DEPTH >= 1 && DEPTH <= 12, "gather pipeline depth 1..12");
     static_assert(DEPTH >= 2 || !JAC, "the Jacobian sums need a pipeline depth of at least 2");
+    static_assert(!(JAC && COUNT), "the folded Jacobian loop does not count segments");
     constexpr int derived = DERIVED;
     RayAcc r;
     r.sum = 0.0;

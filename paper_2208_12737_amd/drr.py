@@ -130,6 +130,48 @@ class Volume:
         return self.packed.numel() * 4
 
 
+def choose_layout(data: torch.Tensor, spacing, det: "Detector", poses: torch.Tensor, origin=None,
+                  device=None, max_bytes: int | None = None, reps: int = 5):
+    """Pack `data` in each layout whose packed size fits `max_bytes`, time the
+    forward render of `poses` on `det` from each (median of `reps` launches
+    after two warm-ups, HIP events on the current stream), and return the
+    Volume in the fastest layout and the times {layout: ms}.  The layouts give
+    bitwise the same images; they differ in speed (each copy has the
+    principal axis of the rays that read it slowest in memory) and in size
+    (three copies or one)."""
+    p = _poses(poses)
+    times = {}
+    best = None
+    for name in ("per_axis", "input"):
+        if max_bytes is not None:
+            shape = tuple(int(v) for v in data.shape)
+            org = origin if origin is not None else tuple(-0.5 * n * float(s)
+                                                          for n, s in zip(shape, spacing))
+            desc = _lib.volume_desc(shape, spacing, org, LAYOUTS[name])
+            if _lib.load().drr_volume_packed_bytes(ctypes.byref(desc)) > max_bytes:
+                continue
+        vol = Volume(data, spacing, origin, device=device, layout=name)
+        for _ in range(2):
+            render(vol, p, det)
+        out = []
+        for _ in range(max(1, int(reps))):
+            a = torch.cuda.Event(enable_timing=True)
+            b = torch.cuda.Event(enable_timing=True)
+            a.record()
+            render(vol, p, det)
+            b.record()
+            b.synchronize()
+            out.append(a.elapsed_time(b))
+        out.sort()
+        times[name] = out[len(out) // 2]
+        if best is None or times[name] < times[best.layout]:
+            best = vol
+        del vol
+    if best is None:
+        raise ValueError(f"no volume layout fits in {max_bytes} bytes")
+    return best, times
+
+
 def render(volume: Volume, poses: torch.Tensor, det: Detector, jacobian: bool = False):
     """DRRs [n, H, W] (and, if asked, Jacobians [n, H, W, 7])."""
     p = _poses(poses)

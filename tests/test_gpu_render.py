@@ -278,6 +278,34 @@ def test_largest_serving_volume_and_detector():
     torch.cuda.empty_cache()
 
 
+def test_choose_layout(small):
+    """The layout tuner times both packings, keeps the faster, and the kept
+    volume renders exactly as the single-copy layout; a byte budget that only
+    the single copy fits leaves it the only candidate, and one that nothing
+    fits is an error."""
+    P = _lib_objs()
+    ph, _, grid = small
+    det = P.Detector(40, 36, 2.0, 2.0)
+    poses = _gpu(random_poses(6, math.pi / 4, 8.0, 900.0, seed=12))
+    data = torch.from_numpy(ph.volume)
+    vol, times = P.choose_layout(data, ph.spacing, det, poses, origin=ph.origin, device=DEV)
+    assert set(times) == {"per_axis", "input"} and all(t > 0 for t in times.values())
+    assert vol.layout == min(times, key=times.get)
+    one = P.Volume(data, ph.spacing, ph.origin, device=DEV, layout="input")
+    ref = P.render(one, poses, det)
+    assert torch.equal(P.render(vol, poses, det), ref)
+    assert_image_close(ref.cpu().numpy(),
+                       oracle.render(grid, poses.cpu().numpy().astype(np.float64), 40, 36,
+                                     2.0, 2.0)[0])
+    v2, t2 = P.choose_layout(data, ph.spacing, det, poses, origin=ph.origin, device=DEV,
+                             max_bytes=one.nbytes, reps=2)
+    assert v2.layout == "input" and set(t2) == {"input"}
+    assert torch.equal(P.render(v2, poses, det), ref)
+    with pytest.raises(ValueError):
+        P.choose_layout(data, ph.spacing, det, poses, origin=ph.origin, device=DEV,
+                        max_bytes=1024)
+
+
 def test_layouts_render_identically(small, ct512):
     """The per-axis copies only change memory order: renders, counts and
     Jacobians are bitwise equal to the single-copy layout, for poses whose
