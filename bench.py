@@ -48,7 +48,7 @@ def parse():
     ap.add_argument("--only", choices=["fwd", "fwdbwd", "direct"], default=None,
                     help="time one phase only (for profiling runs)")
     ap.add_argument("--mode", choices=["drr", "register", "serve", "landscape", "table1",
-                                       "gather-calibration", "long-volume"],
+                                       "gather-calibration", "long-volume", "single"],
                     default="drr",
                     help="drr: the headline forward / fwd+bwd batch (default); register: "
                          "32 batched registrations; serve: the request loop over four "
@@ -57,7 +57,8 @@ def parse():
                          "formulations beside the kernel; gather-calibration: cost of one "
                          "gather instruction against the cache lines it touches; long-volume: "
                          "forward batches on the 512 x 512 x 300 CT, which does not fit the "
-                         "Infinity Cache")
+                         "Infinity Cache; single: --steps single-DRR launches of one "
+                         "benchmark pose (for profiling the one-workgroup-per-CU launch)")
     ap.add_argument("--requests", type=int, default=2000,
                     help="requests per QPS point in --mode serve (and of the serving point of "
                          "the default mode)")
@@ -374,6 +375,47 @@ def plain_single_drr_path(vols, reqs):
     lat = np.array(lat)
     return {"rps": float(1e3 / lat.mean()), "p50_ms": float(np.percentile(lat, 50)),
             "p99_ms": float(np.percentile(lat, 99)), "requests": len(lat)}
+
+
+def bench_single(args):
+    """Single-DRR launches (one 256 x 256 DRR of the 512 x 512 x 133 CT per
+    drr_render call, one workgroup per CU): host latency from launch to
+    completion and device time, --steps launches after 20 warm-ups."""
+    import torch
+    import paper_2208_12737_amd as P
+    import paper_2208_12737_amd._lib as L
+    from synth import make_phantom, random_poses
+    ph = make_phantom("ct512", seed=0)
+    vol = P.Volume(torch.from_numpy(ph.volume), ph.spacing, ph.origin, device="cuda")
+    det = P.Detector(256, 256, 1.4, 1.4)
+    one = torch.from_numpy(random_poses(1, math.pi / 6, 30.0, 1020.0, seed=1)).cuda()
+    img = torch.empty((1, 256, 256), dtype=torch.float32, device="cuda")
+    stream = torch.cuda.current_stream()
+
+    def launch():
+        L.call("drr_render", vol.packed.data_ptr(), ctypes.byref(vol.desc), ctypes.byref(det.desc),
+               one.data_ptr(), 1, img.data_ptr(), None, stream.cuda_stream)
+    for _ in range(20):
+        launch()
+    torch.cuda.synchronize()
+    host, dev = [], []
+    for _ in range(max(args.steps, 1)):
+        a = torch.cuda.Event(enable_timing=True)
+        b = torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        a.record(stream)
+        launch()
+        b.record(stream)
+        torch.cuda.synchronize()
+        host.append((time.perf_counter() - t) * 1e3)
+        dev.append(a.elapsed_time(b))
+    _, cnt = P.render_count(vol, one, det)
+    res = {"metric": "single-DRR latency (ms)", "mode": "single", "launches": len(host),
+           "host_p50_ms": float(np.percentile(host, 50)), "host_p99_ms": float(np.percentile(host, 99)),
+           "device_p50_ms": float(np.percentile(dev, 50)),
+           "gathers": int(cnt.to(torch.int64).sum().item()), "data": "synthetic"}
+    print(json.dumps(res), flush=True)
 
 
 def serving_volumes():
@@ -765,6 +807,9 @@ def main():
         return
     if args.mode == "gather-calibration":
         bench_gather_calibration(args)
+        return
+    if args.mode == "single":
+        bench_single(args)
         return
     if args.mode == "long-volume":
         import torch

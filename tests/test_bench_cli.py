@@ -25,7 +25,8 @@ def test_more_than_one_gpu_is_refused_with_a_message():
 def test_defaults_and_modes():
     r = _run("--help")
     assert r.returncode == 0
-    for mode in ("drr", "register", "serve", "landscape", "table1", "gather-calibration"):
+    for mode in ("drr", "register", "serve", "landscape", "table1", "gather-calibration",
+                 "long-volume", "single"):
         assert mode in r.stdout
     sys.path.insert(0, ROOT)
     import bench
