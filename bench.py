@@ -1112,9 +1112,13 @@ def main():
         # algorithmic bytes of the fused kernel: gathers + the target read
         # (losses and gradients are a few bytes per pose)
         fb_bytes = 4 * gathers_bwd + 4 * pixels
-        res["fwdbwd_roofline"] = {"bound": "valu", "algorithmic_GBps": fb_bytes / t_fb / 1e9,
+        res["fwdbwd_roofline"] = {"bound": "hbm", "algorithmic_GBps": fb_bytes / t_fb / 1e9,
                                   "hbm_frac": fb_bytes / t_fb / 8.0e12,
-                                  "bytes_per_launch": fb_bytes}
+                                  "bytes_per_launch": fb_bytes,
+                                  "achieved_is": "algorithmic bytes (4 B per voxel gather + 4 B "
+                                                 "per target pixel) / event-timed launch",
+                                  "limiter": "texture addresser and VALU issue together (see "
+                                             "profiles/render_ncc_grad_ct512_det256_poses256.md)"}
         if "value" not in res:
             res["value"] = nb / t_fb
     res["step_p50_ms"] = float(np.percentile(step_ms, 50))
